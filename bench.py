@@ -1,0 +1,214 @@
+"""Throughput benchmark of the ensemble CN/RK3 step on one MI355X.
+
+One "step" is one full time step (three RK3 sub-steps: advection stage, right-
+hand sides, CN solves, velocity recovery, diagnostics) of every member of the
+ensemble, on synthetic seeded initial conditions already resident in HBM.
+
+Default workload: plane Poiseuille flow at constant flux, Re = 4200 (laminar
+centreline; bulk Re 5600, the Re_tau ~ 180 case), box 2pi x 2 x pi,
+64 x 97 x 64 modes/points, 16 members, dt = 0.005, mixed precision
+(FFT and y-derivative products in FP32, implicit solves in FP64), each step
+replayed as one hipGraph.
+
+Prints ONE JSON line with member-steps/s, the roofline fraction of the
+dominant kernel (timed live with HIP events on the library's stream), and the
+CPU oracle timed on this host as a reported baseline.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Vector ALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.  Packed
+# FP32 is disabled in this build, so FP32 and FP64 vector peaks are equal.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--workload", default="channel-re4200-64x97x64-e16")
+    ap.add_argument("--ensemble", type=int, default=None)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def kernel_model(w, E, precision):
+    """Algorithmic bytes and flops of one launch of each hot kernel."""
+    Nx, Ny, Nz = w["Nx"], w["Ny"], w["Nz"]
+    L, P, NZ, My, N = Nx // 2, Nz // 2, Nz - 1, Ny, Ny - 2
+    K, G = L * NZ, L * P
+    Mx, Mz = 3 * L, 3 * P
+    vt = 8 if precision == "fp64" else 4
+    cplx = 2 * vt
+    # advection kernel: read u,v,w,uy,wy spectra, write Nu,Nv,Nw spectra, plane means
+    plane_bytes = (5 + 3) * My * K * E * cplx + 2 * My * E * 8
+    # flops: complex FFT 5 n log2 n, real FFT 2.5 n log2 n (conventional counts)
+    zinv = 8 * L * 5 * Mz * np.log2(Mz)
+    xinv = 11 * Mz * 2.5 * Mx * np.log2(Mx)
+    prod = Mx * Mz * (3 * 5 + 2 * 2)
+    xfwd = 3 * Mz * 2.5 * Mx * np.log2(Mx)
+    zfwd = 3 * L * 5 * Mz * np.log2(Mz)
+    plane_flops = (zinv + xinv + prod + xfwd + zfwd) * My * E
+    # per-(kx,kz) kernel (second sub-step): N spectra in, velocity spectra out,
+    # state and history in FP64, operators A_v, B_v, A_eta, B_eta once per group
+    mode_bytes = (3 + 5) * My * K * E * cplx + 2 * K * N * E * 16 + 2 * 2 * K * N * E * 16 \
+        + G * 4 * N * N * 8
+    cols = 2 * K * E  # real columns over all modes
+    mode_flops = cols * (2 * 2 * N * N * 2 + My * My * 2 + My * N * 2 + 2 * My * My * 2)
+    return {"plane": (plane_bytes, plane_flops), "mode": (mode_bytes, mode_flops)}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_12739_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only if
+    they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    rec = d.get("kernels", {}).get(f"{kernel}/{workload}/{precision}")
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, name):
+    """The oracle as it stands, on this host: 2 members x 3 steps of the workload."""
+    import oracle
+    from paper_2306_12739_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    members, steps = 2, 3
+    sim = oracle.OracleDNS(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"],
+                           members, w["dt"])
+    sim.set_state(*inputs.workload_state(name, ensemble=members))
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": members * steps / dt, "unit": "member-steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{members} members x {steps} steps of {name} (numpy FP64, operators prebuilt)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (the ensemble shards by members across GPUs "
+              f"with no exchange; a multi-GPU run is not built here). Got --gpus {args.gpus}.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2306_12739_amd import dns, inputs
+
+    name = args.workload
+    w = inputs.WORKLOADS[name]
+    E = args.ensemble or w["ensemble"]
+    torch.cuda.set_device(0)
+    # a dedicated stream (default priority): the library launches on it and the
+    # timing events are recorded on it
+    stream = torch.cuda.Stream()
+    ens = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], E, w["dt"])
+    ens.set_stream(stream)
+    ens.set_precision(dns.PREC_FP64 if args.precision == "fp64" else dns.PREC_MIXED_FP32)
+    ens.set_option(dns.OPT_GRAPH, 0 if args.no_graph else 1)
+    ens.set_state(*inputs.workload_state(name, ensemble=E))
+
+    ens.step(args.warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    ens.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    if abs(ms / 1e3 - wall) > 0.2 * wall + 0.05:
+        print(f"warning: event time {ms / 1e3:.3f}s vs wall {wall:.3f}s", file=sys.stderr)
+    s = ens.stats(allow_nonfinite=True)
+    if s["rc"] != 0:
+        print(f"warning: {int(s['failed'].sum())} members non-finite", file=sys.stderr)
+
+    plane_ms, mode_ms = ens.kernel_times(args.kernel_reps)
+    ens.close()
+
+    ms_step = ms / args.steps
+    value = E * args.steps / (ms / 1e3)
+    gp_paper = (w["Nx"] - 1) * (w["Nz"] - 1) * (w["Ny"] - 2)
+    model = kernel_model(w, E, args.precision)
+    per_kernel = {}
+    for k, t in (("plane", plane_ms), ("mode", mode_ms)):
+        b, f = model[k]
+        per_kernel[k] = {"ms": t, "GB/s": b / (t * 1e-3) / 1e9, "TFLOP/s": f / (t * 1e-3) / 1e12,
+                         "alg_bytes": b, "alg_flops": f}
+    dom = "plane" if plane_ms >= mode_ms else "mode"
+    pk = per_kernel[dom]
+    if dom == "plane":
+        roof = {"bound": "alu", "achieved": pk["TFLOP/s"], "peak": VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": pk["TFLOP/s"] / VALU_PEAK_TFLOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": pk["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": pk["GB/s"] / HBM_PEAK_GBS}
+    roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom, name, args.precision)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, name)
+    out = {
+        "metric": "ensemble member-steps/s at Re_tau~180; mixed vs FP64 at <=1% stats error",
+        "value": value,
+        "unit": "member-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "flow": "poiseuille" if w["flow"] else "couette",
+                   "Re": w["Re"], "grid": f"{w['Nx']}x{w['Ny']}x{w['Nz']}", "ensemble": E,
+                   "dt": w["dt"], "precision": args.precision, "graph": not args.no_graph},
+        "grid_point_steps_per_s": value * gp_paper,
+        "grid_point_steps_per_s_nominal": value * w["Nx"] * w["Ny"] * w["Nz"],
+        "wall_s": wall,
+        "kernels": per_kernel,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

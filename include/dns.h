@@ -1,0 +1,217 @@
+/*
+ * Ensemble DNS of plane Couette and plane Poiseuille flow on one MI355X GPU.
+ *
+ * C ABI of the HIP library libdns_ensemble.so.  The solver advances an ensemble
+ * of independent flow realisations of the incompressible Navier-Stokes
+ * equations between two parallel walls (arXiv 2306.12739, Sec. 2, Eqs. (1)-(3)),
+ * written for the wall-normal velocity v and vorticity eta with the mean
+ * profiles U00, W00 (Eqs. (Dv), (eta), (U00), (W00)), discretised with Fourier
+ * modes in x and z and Chebyshev collocation in y (Sec. 2), and integrated with
+ * the CN/RK3 scheme of Sec. 3.1 using pre-inverted per-(kx,kz) operators
+ * (Sec. 3.2, Eqs. (CN1)-(CN4)).  All ensemble members share the grid, box,
+ * Reynolds number and time step; members are independent (Sec. 3.2, last
+ * paragraph: members are extra columns of every operator application).
+ *
+ * Conventions shared by all calls
+ *   - Walls at y = -1 and y = +1 (half width h = 1); Re = U h / nu with U the
+ *     Couette wall speed or the laminar channel centreline speed (Sec. 2).
+ *   - Nx, Nz: even Fourier sizes; stored modes n_x = 0..Nx/2-1 and
+ *     |n_z| <= Nz/2-1 (2/3-rule de-aliasing, Sec. 3.2, done as 3/2 padding:
+ *     the physical grid has 3Nx/2 x 3Nz/2 points).  Ny: Chebyshev-Gauss-Lobatto
+ *     points y_j = -cos(pi j/(Ny-1)), j = 0..Ny-1, walls included.
+ *   - Spectral normalisation: f_hat(k) = 1/(Mx Mz) sum f e^{-i(kx x + kz z)},
+ *     so f_hat(0,0) is the plane mean.
+ *   - Every call returns DNS_OK (0) or a negative DNS_E_* code and records a
+ *     message retrievable with dns_last_error().
+ *   - Handles are not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef DNS_ENSEMBLE_H
+#define DNS_ENSEMBLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DNS_OK 0
+#define DNS_E_INVALID (-1)     /* bad argument or unsupported combination       */
+#define DNS_E_NOMEM (-2)       /* device or host allocation failed              */
+#define DNS_E_HIP (-3)         /* a HIP runtime call failed                     */
+#define DNS_E_NONFINITE (-4)   /* at least one member produced NaN/Inf          */
+#define DNS_E_UNSUPPORTED (-5) /* valid but not built (grid size, precision)    */
+#define DNS_E_STATE (-6)       /* call-order misuse (e.g. NULL handle)          */
+
+#define DNS_FLOW_COUETTE 0
+#define DNS_FLOW_POISEUILLE 1
+
+typedef struct dns_handle dns_handle;
+
+/* Problem statement of Sec. 2: box and wall forcing.
+ *   flow : DNS_FLOW_COUETTE (walls at y = -1/+1 move at -Uw/+Uw, gamma = 0) or
+ *          DNS_FLOW_POISEUILLE (walls at rest, gamma(t) holds the bulk flux).
+ *   Lx, Lz : periodic box lengths (k_x = 2 pi n / Lx, k_z = 2 pi m / Lz).
+ *   Uw   : Couette wall speed (default 1 when <= 0).
+ *   flux : channel bulk flux target int_{-1}^{1} U dy (4/3 when <= 0, the
+ *          laminar parabola U = 1 - y^2). */
+typedef struct {
+  int flow;
+  double Lx, Lz;
+  double Uw;
+  double flux;
+} dns_geometry;
+
+/* Create an ensemble solver (Sec. 3.2: operators are built once per (kx,kz) and
+ * h in {1/2, 1}, on the host in extended precision, then uploaded).
+ *   Nx, Nz : 16, 32, 48 or 64 with Nx == Nz;  Ny : 5..257 (odd or even);
+ *   ensemble >= 1; dt > 0; Re > 0.
+ * The state is initialised to the laminar profile (Couette U = Uw y, channel
+ * U = 1 - y^2) with zero perturbations.  Device memory is owned by the handle.
+ * On failure *out is set to NULL.  Errors: DNS_E_INVALID, DNS_E_UNSUPPORTED,
+ * DNS_E_NOMEM, DNS_E_HIP. */
+int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ensemble, double dt,
+               dns_handle** out);
+
+/* Options (dns_set_option keys) */
+#define DNS_OPT_PRECISION 1   /* value: DNS_PREC_*                                */
+#define DNS_OPT_STREAM 2      /* value: hipStream_t cast to integer (0 = default) */
+#define DNS_OPT_GRAPH 3       /* value: 1 capture one step as a hipGraph, 0 eager */
+#define DNS_OPT_STATS 4       /* value: 1 accumulate one-point statistics each step */
+
+#define DNS_PREC_FP64 0        /* every stage in FP64                               */
+#define DNS_PREC_MIXED_FP32 1  /* y-derivative products and x-z FFTs in FP32, FP32
+                                  stage buffers; implicit solves, mean flow and
+                                  flux update in FP64                              */
+
+/* Set an option.  Precision may be changed between steps (the stage buffers
+ * are re-derived from the FP64 state).  Errors: DNS_E_INVALID. */
+int dns_set_option(dns_handle* h, int key, long long value);
+
+/* Host or device view of ensemble states.
+ *   v_hat, eta_hat : interleaved complex double,
+ *                    [member][n_x 0..Nx/2-1][n_z FFT order][j 1..Ny-2]
+ *                    where FFT order is n_z = 0..Nz/2-1 then -(Nz/2-1)..-1
+ *                    (Nz-1 entries); interior Chebyshev nodes only (v = eta = 0
+ *                    at the walls, Eq. (b_ve)).  The n_x = 0 column must be
+ *                    Hermitian (f(0,-n_z) = conj f(0,n_z)); (0,0) must be 0.
+ *   U00, W00       : double [member][j 0..Ny-1], walls included.
+ *   on_device      : 0 host pointers, 1 device pointers (same layout).
+ * The caller owns the buffers; the library copies. */
+typedef struct {
+  double* v_hat;
+  double* eta_hat;
+  double* U00;
+  double* W00;
+  int on_device;
+} dns_state_view;
+
+/* Load members [member0, member0+count) from s.  Wall values of U00/W00 must
+ * match the boundary conditions (Couette U00(-1) = -Uw, U00(1) = Uw; channel
+ * 0; W00 = 0) within 1e-12.  Clears the members' failure flags.
+ * Errors: DNS_E_INVALID. */
+int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s);
+
+/* Copy members [member0, member0+count) into s (synchronises the stream). */
+int dns_get_state(dns_handle* h, int member0, int count, dns_state_view* s);
+
+/* Advance every member by nsteps CN/RK3 time steps (Sec. 3.1), asynchronously
+ * on the handle's stream.  A member that produces NaN/Inf is flagged
+ * (sticky) and reported by dns_stats / dns_sync as DNS_E_NONFINITE; the other
+ * members are unaffected (members never exchange data).  Errors: DNS_E_HIP. */
+int dns_step(dns_handle* h, int nsteps);
+
+/* Per-member diagnostics of the current state and time/ensemble-averaged
+ * one-point statistics (Sec. 4: mean profile U(y), rms u', v', w' about it,
+ * Reynolds stress u'v').  Any pointer may be NULL.  Arrays of length
+ * `ensemble` (per member) or Ny (profiles) are owned by the caller.
+ * Volume averages use Clenshaw-Curtis weights over y and divide by Ly = 2.
+ *   energy      E = 1/(2V) int |u|^2 (mean flow included)
+ *   dissipation eps = 1/(Re V) int |grad u|^2
+ *   power       Couette Uw (U'(1) + U'(-1)) / (Re Ly); channel gamma Q / Ly
+ *   flux        Q = int U dy;  gamma: pressure gradient of the last sub-step
+ *   div_max     max over modes/nodes of |i kx u + dv/dy + i kz w|
+ *   tau_lower/upper  U'(-1)/Re and U'(+1)/Re;  failed: sticky NaN/Inf flag
+ *   profiles    averaged over members and the samples since the last reset;
+ *   tau_w       Couette mean |U'| at the walls / Re, channel (U'(-1)-U'(1))/(2Re)
+ *   re_tau      Re sqrt(tau_w)
+ * Synchronises.  Returns DNS_E_NONFINITE if any member failed, else DNS_OK. */
+typedef struct {
+  double* energy;
+  double* dissipation;
+  double* power;
+  double* flux;
+  double* gamma;
+  double* div_max;
+  double* tau_lower;
+  double* tau_upper;
+  int* failed;
+  double* U;
+  double* W;
+  double* urms;
+  double* vrms;
+  double* wrms;
+  double* uv;
+  double tau_w;
+  double re_tau;
+  long long samples;
+  long long steps;
+} dns_stats_out;
+int dns_stats(dns_handle* h, dns_stats_out* o);
+
+/* Restart the time averages of dns_stats. */
+int dns_stats_reset(dns_handle* h);
+
+/* Wait for all queued work; DNS_E_NONFINITE if a member has failed. */
+int dns_sync(dns_handle* h);
+
+/* Free every resource of the handle.  NULL-safe. */
+void dns_destroy(dns_handle* h);
+
+/* Message of the last error on h (or of the calling thread when h is NULL). */
+const char* dns_last_error(const dns_handle* h);
+
+/* Stage intermediates for verification (not needed for time stepping).
+ * From the current state, without advancing it, computes the first RK3
+ * sub-step's inputs and copies them to host buffers (NULL skips):
+ *   vel   : complex double [5][member][Ny][Nx/2][Nz-1]: u, v, w, du/dy, dw/dy
+ *           (Sec. 3.2 u/w recovery and y derivatives);
+ *   nl    : complex double [3][member][Ny][Nx/2][Nz-1]: de-aliased advection
+ *           terms u.grad u, u.grad v, u.grad w (Sec. 3.1);
+ *   means : double [2][member][Ny]: plane means <uv>, <wv> (Eqs. (U00), (W00)).
+ * Synchronises.  Errors: DNS_E_HIP. */
+int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means);
+
+/* Average device time of one launch of each hot kernel, measured with HIP
+ * events on the handle's stream over nreps back-to-back launches at the
+ * current precision (Sec. 4.4 times the same operation classes of one step).
+ * Does not advance the state: the second RK3 sub-step's kernels are timed
+ * against the current stage buffers and the next dns_step re-derives them.
+ * Outputs, milliseconds per launch (NULL skips):
+ *   plane_ms : de-aliased advection kernel (x-z FFTs and products, Sec. 3.1);
+ *   mode_ms  : per-(kx,kz) right-hand side, CN solve and velocity kernel
+ *              (Eqs. (CN1)-(CN4)).
+ * Synchronises.  Errors: DNS_E_INVALID (nreps < 1), DNS_E_HIP. */
+int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms);
+
+/* Host-side operator construction for verification; needs no GPU.
+ * Builds on the host, in extended precision, exactly the operators dns_create
+ * uploads for one sub-step fraction (h_index 0: h = 1/2, 1: h = 1), with
+ * c = h dt / (2 Re) (Sec. 3.2, Eqs. (CN1)-(CN4), Listings 1 and 3):
+ *   ops      : double [Nx/2 * Nz/2][4][Ny-2][Ny-2], row-major; per group
+ *              g = n_x*(Nz/2) + |n_z| the folded A_v, B_v, A_eta, B_eta with
+ *              v_new = A_v v0 - h dt B_v F and eta_new = A_eta eta0 - h dt B_eta G;
+ *              group 0 (the mean) is zero;
+ *   mean_ops : double [2][Ny-2][Ny-2]: A_U, B_U of the mean profiles;
+ *   lift     : double [Ny-2]: Couette wall-velocity contribution to U;
+ *   green    : double [Ny-2]: response of U to a unit pressure gradient gamma;
+ *   D1       : double [Ny][Ny] Chebyshev first derivative (ascending nodes);
+ *   D1c      : double [Ny][Ny-2] first derivative of the clamped interpolant;
+ *   ccw      : double [Ny] Clenshaw-Curtis weights.
+ * NULL outputs are skipped.  Errors: DNS_E_INVALID, DNS_E_UNSUPPORTED. */
+int dns_host_operators(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, double dt,
+                       int h_index, double* ops, double* mean_ops, double* lift, double* green,
+                       double* D1, double* D1c, double* ccw);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DNS_ENSEMBLE_H */

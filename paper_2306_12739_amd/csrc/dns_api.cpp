@@ -1,0 +1,714 @@
+// C ABI of the ensemble DNS library: handle lifetime, state I/O, the CN/RK3
+// step orchestration and statistics.  See include/dns.h for the contract.
+//
+// One time step (paper Sec. 3.1) is three sub-steps s = 0, 1, 2 with
+// h = 1/2, 1, 1.  Each sub-step is two kernels:
+//   plane kernel  (one workgroup per Chebyshev plane and member): velocity
+//                 fields -> 3/2-padded physical grid -> u.grad u -> truncated
+//                 spectrum, plane means <uv>, <wv>;
+//   mode kernel   (one workgroup per (nx, |nz|) operator group and member
+//                 tile): F, G, RK3 combination, FP64 CN solves, velocities of
+//                 the next sub-step's state.
+// After sub-step 0's plane kernel a small kernel evaluates per-member
+// diagnostics (and, when enabled, accumulates one-point statistics) of the
+// state at the start of the step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dns.h"
+#include "internal.h"
+
+using namespace dns;
+
+struct dns_handle {
+  // problem
+  int flow = 0;
+  double Lx = 0, Lz = 0, Uw = 1, flux = 4.0 / 3.0, Re = 0, dt = 0;
+  int Nx = 0, Ny = 0, Nz = 0, E = 0;
+  int L = 0, P = 0, NZ = 0, K = 0, N = 0, My = 0, G = 0;
+  double kxs = 0, kzs = 0, Ubot = 0, Utop = 0;
+  // options
+  int precision = DNS_PREC_FP64;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  bool use_graph = false;
+  bool stats_on = false;
+  // device buffers
+  double *v = nullptr, *eta = nullptr, *U = nullptr, *W = nullptr;
+  double *hF = nullptr, *hG = nullptr, *hEU = nullptr, *hEW = nullptr;
+  void *vel = nullptr, *nl = nullptr;
+  double *means = nullptr, *psum = nullptr;
+  double *ops[2] = {nullptr, nullptr}, *mean_ops[2] = {nullptr, nullptr};
+  double *lift[2] = {nullptr, nullptr}, *green[2] = {nullptr, nullptr};
+  double *D1 = nullptr, *D1c = nullptr, *ccw = nullptr;
+  double* gamma = nullptr;
+  int* failed = nullptr;
+  unsigned long long* divmax = nullptr;
+  double *acc = nullptr, *inst = nullptr;
+  double* staging = nullptr;
+  size_t staging_bytes = 0;
+  int ET = 1, ntiles = 1;
+  // progress
+  long long steps = 0, samples = 0;
+  bool vel_fresh = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_valid = false;
+  double max_cond = 0.0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+int fail(dns_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg; else g_thread_err = msg;
+  return code;
+}
+
+#define HIP_OR_FAIL(h, call)                                                              \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((h), DNS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+size_t vt_size(int precision) { return precision == DNS_PREC_FP64 ? sizeof(double) : sizeof(float); }
+
+void free_all(dns_handle* h) {
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  void* bufs[] = {h->v, h->eta, h->U, h->W, h->hF, h->hG, h->hEU, h->hEW, h->vel, h->nl,
+                  h->means, h->psum, h->ops[0], h->ops[1], h->mean_ops[0], h->mean_ops[1],
+                  h->lift[0], h->lift[1], h->green[0], h->green[1], h->D1, h->D1c, h->ccw,
+                  h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging};
+  for (void* p : bufs)
+    if (p) hipFree(p);
+  if (h->own_stream) hipStreamDestroy(h->own_stream);
+}
+
+int ensure_staging(dns_handle* h, size_t bytes) {
+  if (bytes <= h->staging_bytes) return DNS_OK;
+  if (h->staging) hipFree(h->staging);
+  h->staging = nullptr;
+  h->staging_bytes = 0;
+  HIP_OR_FAIL(h, hipMalloc(reinterpret_cast<void**>(&h->staging), bytes));
+  h->staging_bytes = bytes;
+  return DNS_OK;
+}
+
+ModeArgs mode_args(dns_handle* h, int stage) {
+  ModeArgs a{};
+  const int hi = stage == 0 ? 0 : 1;
+  const double hval = stage == 0 ? 0.5 : 1.0;
+  a.v = h->v;
+  a.eta = h->eta;
+  a.U = h->U;
+  a.W = h->W;
+  a.hF = h->hF;
+  a.hG = h->hG;
+  a.hEU = h->hEU;
+  a.hEW = h->hEW;
+  a.vel = h->vel;
+  a.nl = h->nl;
+  a.means = h->means;
+  a.ops = h->ops[hi];
+  a.mean_ops = h->mean_ops[hi];
+  a.lift = h->lift[hi];
+  a.green = h->green[hi];
+  a.D1 = h->D1;
+  a.D1c = h->D1c;
+  a.ccw = h->ccw;
+  a.gamma = h->gamma;
+  a.failed = h->failed;
+  a.divmax = h->divmax;
+  a.My = h->My;
+  a.N = h->N;
+  a.K = h->K;
+  a.E = h->E;
+  a.L = h->L;
+  a.P = h->P;
+  a.NZ = h->NZ;
+  a.G = h->G;
+  a.ET = h->ET;
+  a.ntiles = h->ntiles;
+  a.kxs = h->kxs;
+  a.kzs = h->kzs;
+  a.hdt = hval * h->dt;
+  a.Ubot = h->Ubot;
+  a.Utop = h->Utop;
+  a.Qtarget = h->flux;
+  a.stage = stage;
+  a.poiseuille = h->flow == DNS_FLOW_POISEUILLE;
+  return a;
+}
+
+PlaneArgs plane_args(dns_handle* h, bool sums) {
+  PlaneArgs a{};
+  a.vel = h->vel;
+  a.nl = h->nl;
+  a.means = h->means;
+  a.psum = sums ? h->psum : nullptr;
+  a.My = h->My;
+  a.K = h->K;
+  a.E = h->E;
+  a.kxs = h->kxs;
+  a.kzs = h->kzs;
+  return a;
+}
+
+StatsArgs stats_args(dns_handle* h) {
+  StatsArgs a{};
+  a.psum = h->psum;
+  a.means = h->means;
+  a.U = h->U;
+  a.W = h->W;
+  a.ccw = h->ccw;
+  a.D1 = h->D1;
+  a.gamma = h->gamma;
+  a.acc = h->acc;
+  a.inst = h->inst;
+  a.failed = h->failed;
+  a.My = h->My;
+  a.E = h->E;
+  a.Re = h->Re;
+  a.Uw = h->Uw;
+  a.poiseuille = h->flow == DNS_FLOW_POISEUILLE ? 1.0 : 0.0;
+  a.Qtarget = h->flux;
+  return a;
+}
+
+// Velocity fields of the current state (no time advance).
+int refresh_velocities(dns_handle* h) {
+  HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, -1), h->stream));
+  h->vel_fresh = true;
+  return DNS_OK;
+}
+
+// Enqueue one time step; requires the velocity buffer to hold the state's velocities.
+int enqueue_step(dns_handle* h) {
+  for (int s = 0; s < 3; ++s) {
+    HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, s == 0), h->stream));
+    if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h), h->stats_on ? 1 : 0, h->stream));
+    HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s), h->stream));
+  }
+  return DNS_OK;
+}
+
+void invalidate_graph(dns_handle* h) {
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->graph_valid = false;
+}
+
+int build_graph(dns_handle* h) {
+  invalidate_graph(h);
+  HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_step(h);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (rc != DNS_OK) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(h, DNS_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  h->graph = g;
+  HIP_OR_FAIL(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+  h->graph_valid = true;
+  return DNS_OK;
+}
+
+int any_failed(dns_handle* h, std::vector<int>* flags) {
+  std::vector<int> f(h->E, 0);
+  if (hipMemcpyAsync(f.data(), h->failed, sizeof(int) * h->E, hipMemcpyDeviceToHost, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return -1;
+  int any = 0;
+  for (int x : f) any |= x;
+  if (flags) *flags = f;
+  return any;
+}
+
+int check_dims(int Nx, int Ny, int Nz, int E) {
+  if (Nx <= 0 || Nz <= 0 || (Nx % 2) || (Nz % 2)) return DNS_E_INVALID;
+  if (Ny < 5 || Ny > 257) return DNS_E_INVALID;
+  if (E < 1) return DNS_E_INVALID;
+  if (!plane_supported(Nx, Nz)) return DNS_E_UNSUPPORTED;
+  return DNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ensemble, double dt,
+               dns_handle** out) {
+  if (!out) return fail(nullptr, DNS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(nullptr, DNS_E_INVALID, "geometry is NULL");
+  if (g->flow != DNS_FLOW_COUETTE && g->flow != DNS_FLOW_POISEUILLE)
+    return fail(nullptr, DNS_E_INVALID, "unknown flow type");
+  if (!(g->Lx > 0) || !(g->Lz > 0) || !(Re > 0) || !(dt > 0) || !std::isfinite(Re) ||
+      !std::isfinite(dt))
+    return fail(nullptr, DNS_E_INVALID, "Lx, Lz, Re and dt must be positive and finite");
+  const int dc = check_dims(Nx, Ny, Nz, ensemble);
+  if (dc == DNS_E_INVALID)
+    return fail(nullptr, dc, "need even Nx, Nz > 0, 5 <= Ny <= 257 and ensemble >= 1");
+  if (dc == DNS_E_UNSUPPORTED)
+    return fail(nullptr, dc, "grid not built: Nx == Nz in {16, 32, 48, 64} are supported");
+
+  dns_handle* h = new dns_handle();
+  h->flow = g->flow;
+  h->Lx = g->Lx;
+  h->Lz = g->Lz;
+  h->Uw = g->Uw > 0 ? g->Uw : 1.0;
+  h->flux = g->flux > 0 ? g->flux : 4.0 / 3.0;
+  h->Re = Re;
+  h->dt = dt;
+  h->Nx = Nx;
+  h->Ny = Ny;
+  h->Nz = Nz;
+  h->E = ensemble;
+  h->L = Nx / 2;
+  h->P = Nz / 2;
+  h->NZ = Nz - 1;
+  h->K = h->L * h->NZ;
+  h->My = Ny;
+  h->N = Ny - 2;
+  h->G = h->L * h->P;
+  h->kxs = 2.0 * M_PI / g->Lx;
+  h->kzs = 2.0 * M_PI / g->Lz;
+  if (h->flow == DNS_FLOW_COUETTE) {
+    h->Ubot = -h->Uw;
+    h->Utop = h->Uw;
+  }
+  h->ET = mode_member_tile(h->My, h->E);
+  h->ntiles = (h->E + h->ET - 1) / h->ET;
+
+  HostOperators ho;
+  if (build_operators(h->My, h->L, h->P, h->kxs, h->kzs, Re, dt, h->Ubot, h->Utop, &ho) != 0) {
+    delete h;
+    return fail(nullptr, DNS_E_INVALID, "a Crank-Nicolson operator is singular");
+  }
+  h->max_cond = ho.max_cond;
+
+  auto fail_free = [&](int code, const std::string& msg) {
+    free_all(h);
+    delete h;
+    return fail(nullptr, code, msg);
+  };
+#define ALLOC(ptr, n)                                                      \
+  if (dalloc(&(ptr), (n)) != hipSuccess) return fail_free(DNS_E_NOMEM, "hipMalloc " #ptr);
+  const size_t KNE = size_t(h->K) * h->N * h->E;
+  const size_t MyE = size_t(h->My) * h->E;
+  ALLOC(h->v, 2 * KNE);
+  ALLOC(h->eta, 2 * KNE);
+  ALLOC(h->U, MyE);
+  ALLOC(h->W, MyE);
+  ALLOC(h->hF, 2 * KNE);
+  ALLOC(h->hG, 2 * KNE);
+  ALLOC(h->hEU, size_t(h->N) * h->E);
+  ALLOC(h->hEW, size_t(h->N) * h->E);
+  {
+    const size_t velb = size_t(5) * h->My * h->K * h->E * 2 * sizeof(double);
+    const size_t nlb = size_t(3) * h->My * h->K * h->E * 2 * sizeof(double);
+    if (hipMalloc(&h->vel, velb) != hipSuccess) return fail_free(DNS_E_NOMEM, "hipMalloc vel");
+    if (hipMalloc(&h->nl, nlb) != hipSuccess) return fail_free(DNS_E_NOMEM, "hipMalloc nl");
+  }
+  ALLOC(h->means, 2 * MyE);
+  ALLOC(h->psum, size_t(NPS) * MyE);
+  for (int hi = 0; hi < 2; ++hi) {
+    ALLOC(h->ops[hi], ho.ops[hi].size());
+    ALLOC(h->mean_ops[hi], ho.mean_ops[hi].size());
+    ALLOC(h->lift[hi], ho.lift[hi].size());
+    ALLOC(h->green[hi], ho.green[hi].size());
+  }
+  ALLOC(h->D1, ho.D1.size());
+  ALLOC(h->D1c, ho.D1c.size());
+  ALLOC(h->ccw, ho.ccw.size());
+  ALLOC(h->gamma, size_t(h->E));
+  ALLOC(h->failed, size_t(h->E));
+  ALLOC(h->divmax, size_t(h->E));
+  ALLOC(h->acc, size_t(NPA) * MyE + 2 * size_t(h->E));
+  ALLOC(h->inst, size_t(NDI) * h->E);
+#undef ALLOC
+  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+    return fail_free(DNS_E_HIP, "hipStreamCreate");
+  h->stream = h->own_stream;
+
+  auto up = [&](double* dst, const std::vector<double>& src) {
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);
+  };
+  bool ok = true;
+  for (int hi = 0; hi < 2; ++hi) {
+    ok &= up(h->ops[hi], ho.ops[hi]) == hipSuccess;
+    ok &= up(h->mean_ops[hi], ho.mean_ops[hi]) == hipSuccess;
+    ok &= up(h->lift[hi], ho.lift[hi]) == hipSuccess;
+    ok &= up(h->green[hi], ho.green[hi]) == hipSuccess;
+  }
+  ok &= up(h->D1, ho.D1) == hipSuccess;
+  ok &= up(h->D1c, ho.D1c) == hipSuccess;
+  ok &= up(h->ccw, ho.ccw) == hipSuccess;
+  // laminar state, zero history
+  std::vector<double> Ul(MyE, 0.0);
+  for (int j = 0; j < h->My; ++j) {
+    const double y = -std::cos(M_PI * j / (h->My - 1));
+    const double u = h->flow == DNS_FLOW_COUETTE ? h->Uw * y : 1.0 - y * y;
+    for (int e = 0; e < h->E; ++e) Ul[size_t(j) * h->E + e] = u;
+  }
+  if (h->flow == DNS_FLOW_POISEUILLE) {
+    for (int e = 0; e < h->E; ++e) {
+      Ul[e] = 0.0;
+      Ul[size_t(h->My - 1) * h->E + e] = 0.0;
+    }
+  }
+  ok &= up(h->U, Ul) == hipSuccess;
+  ok &= hipMemset(h->v, 0, 2 * KNE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->eta, 0, 2 * KNE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->W, 0, MyE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->hF, 0, 2 * KNE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->hG, 0, 2 * KNE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->gamma, 0, h->E * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->failed, 0, h->E * sizeof(int)) == hipSuccess;
+  ok &= hipMemset(h->divmax, 0, h->E * sizeof(unsigned long long)) == hipSuccess;
+  ok &= hipMemset(h->acc, 0, (size_t(NPA) * MyE + 2 * h->E) * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->means, 0, 2 * MyE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->psum, 0, size_t(NPS) * MyE * sizeof(double)) == hipSuccess;
+  if (!ok) return fail_free(DNS_E_HIP, "uploading operators / initial state failed");
+  if (hipDeviceSynchronize() != hipSuccess) return fail_free(DNS_E_HIP, "hipDeviceSynchronize");
+  *out = h;
+  return DNS_OK;
+}
+
+int dns_set_option(dns_handle* h, int key, long long value) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  switch (key) {
+    case DNS_OPT_PRECISION:
+      if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32)
+        return fail(h, DNS_E_INVALID, "unknown precision");
+      if (value != h->precision) {
+        h->precision = int(value);
+        h->vel_fresh = false;
+        invalidate_graph(h);
+      }
+      return DNS_OK;
+    case DNS_OPT_STREAM:
+      h->stream = value ? reinterpret_cast<hipStream_t>(value) : h->own_stream;
+      invalidate_graph(h);
+      return DNS_OK;
+    case DNS_OPT_GRAPH:
+      h->use_graph = value != 0;
+      invalidate_graph(h);
+      return DNS_OK;
+    case DNS_OPT_STATS:
+      h->stats_on = value != 0;
+      invalidate_graph(h);
+      return DNS_OK;
+  }
+  return fail(h, DNS_E_INVALID, "unknown option key");
+}
+
+int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  if (!s || !s->v_hat || !s->eta_hat || !s->U00 || !s->W00)
+    return fail(h, DNS_E_INVALID, "state view has NULL buffers");
+  if (member0 < 0 || count < 1 || member0 + count > h->E)
+    return fail(h, DNS_E_INVALID, "member range out of bounds");
+  const size_t nspec = size_t(count) * h->K * h->N * 2;
+  const size_t nprof = size_t(count) * h->My;
+  // validate on the host (copy device views back first)
+  std::vector<double> U(nprof), W(nprof), v0;
+  if (s->on_device) {
+    HIP_OR_FAIL(h, hipMemcpy(U.data(), s->U00, nprof * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(h, hipMemcpy(W.data(), s->W00, nprof * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(U.data(), s->U00, nprof * sizeof(double));
+    std::memcpy(W.data(), s->W00, nprof * sizeof(double));
+  }
+  for (int m = 0; m < count; ++m) {
+    const double ub = U[size_t(m) * h->My], ut = U[size_t(m) * h->My + h->My - 1];
+    const double wb = W[size_t(m) * h->My], wt = W[size_t(m) * h->My + h->My - 1];
+    if (std::fabs(ub - h->Ubot) > 1e-12 || std::fabs(ut - h->Utop) > 1e-12 || std::fabs(wb) > 1e-12 ||
+        std::fabs(wt) > 1e-12)
+      return fail(h, DNS_E_INVALID, "U00/W00 wall values do not match the boundary conditions");
+  }
+  int rc = ensure_staging(h, 2 * nspec * sizeof(double));
+  if (rc) return rc;
+  const hipMemcpyKind kind = s->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  double* st = h->staging;
+  HIP_OR_FAIL(h, hipMemcpyAsync(st, s->v_hat, nspec * sizeof(double), kind, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(st + nspec, s->eta_hat, nspec * sizeof(double), kind, h->stream));
+  HIP_OR_FAIL(h, launch_state_to_device(st, h->v, member0, count, h->E, h->K, h->N, h->stream));
+  HIP_OR_FAIL(h, launch_state_to_device(st + nspec, h->eta, member0, count, h->E, h->K, h->N, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(st, U.data(), nprof * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(st + nprof, W.data(), nprof * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, launch_profile_to_device(st, h->U, member0, count, h->E, h->My, h->stream));
+  HIP_OR_FAIL(h, launch_profile_to_device(st + nprof, h->W, member0, count, h->E, h->My, h->stream));
+  HIP_OR_FAIL(h, hipMemsetAsync(h->failed + member0, 0, sizeof(int) * count, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  h->vel_fresh = false;
+  return DNS_OK;
+}
+
+int dns_get_state(dns_handle* h, int member0, int count, dns_state_view* s) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  if (!s || !s->v_hat || !s->eta_hat || !s->U00 || !s->W00)
+    return fail(h, DNS_E_INVALID, "state view has NULL buffers");
+  if (member0 < 0 || count < 1 || member0 + count > h->E)
+    return fail(h, DNS_E_INVALID, "member range out of bounds");
+  const size_t nspec = size_t(count) * h->K * h->N * 2;
+  const size_t nprof = size_t(count) * h->My;
+  int rc = ensure_staging(h, (2 * nspec + 2 * nprof) * sizeof(double));
+  if (rc) return rc;
+  double* st = h->staging;
+  HIP_OR_FAIL(h, launch_state_from_device(h->v, st, member0, count, h->E, h->K, h->N, h->stream));
+  HIP_OR_FAIL(h, launch_state_from_device(h->eta, st + nspec, member0, count, h->E, h->K, h->N, h->stream));
+  HIP_OR_FAIL(h, launch_profile_from_device(h->U, st + 2 * nspec, member0, count, h->E, h->My, h->stream));
+  HIP_OR_FAIL(h, launch_profile_from_device(h->W, st + 2 * nspec + nprof, member0, count, h->E, h->My, h->stream));
+  const hipMemcpyKind kind = s->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIP_OR_FAIL(h, hipMemcpyAsync(s->v_hat, st, nspec * sizeof(double), kind, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(s->eta_hat, st + nspec, nspec * sizeof(double), kind, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(s->U00, st + 2 * nspec, nprof * sizeof(double), kind, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(s->W00, st + 2 * nspec + nprof, nprof * sizeof(double), kind, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  return DNS_OK;
+}
+
+int dns_step(dns_handle* h, int nsteps) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  if (nsteps < 0) return fail(h, DNS_E_INVALID, "nsteps must be >= 0");
+  if (nsteps == 0) return DNS_OK;
+  if (!h->vel_fresh) {
+    int rc = refresh_velocities(h);
+    if (rc) return rc;
+  }
+  if (h->use_graph) {
+    if (!h->graph_valid) {
+      int rc = build_graph(h);
+      if (rc) return rc;
+    }
+    for (int n = 0; n < nsteps; ++n) HIP_OR_FAIL(h, hipGraphLaunch(h->gexec, h->stream));
+  } else {
+    for (int n = 0; n < nsteps; ++n) {
+      int rc = enqueue_step(h);
+      if (rc) return rc;
+    }
+  }
+  h->steps += nsteps;
+  if (h->stats_on) h->samples += nsteps;
+  return DNS_OK;
+}
+
+int dns_sync(dns_handle* h) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  const int any = any_failed(h, nullptr);
+  if (any < 0) return fail(h, DNS_E_HIP, "reading failure flags");
+  if (any) return fail(h, DNS_E_NONFINITE, "a member produced a non-finite value");
+  return DNS_OK;
+}
+
+int dns_stats(dns_handle* h, dns_stats_out* o) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  if (!o) return fail(h, DNS_E_INVALID, "output is NULL");
+  // fresh diagnostics of the current state
+  HIP_OR_FAIL(h, hipMemsetAsync(h->divmax, 0, sizeof(unsigned long long) * h->E, h->stream));
+  int rc = refresh_velocities(h);
+  if (rc) return rc;
+  HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, true), h->stream));
+  HIP_OR_FAIL(h, launch_stats(stats_args(h), 0, h->stream));
+  const int E = h->E, My = h->My;
+  std::vector<double> inst(size_t(NDI) * E), gam(E), acc(size_t(NPA) * My * E + 2 * E);
+  std::vector<unsigned long long> dm(E);
+  std::vector<int> fl(E);
+  HIP_OR_FAIL(h, hipMemcpyAsync(inst.data(), h->inst, inst.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(gam.data(), h->gamma, gam.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(acc.data(), h->acc, acc.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(dm.data(), h->divmax, dm.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(fl.data(), h->failed, fl.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  int anyf = 0;
+  for (int e = 0; e < E; ++e) {
+    if (o->energy) o->energy[e] = inst[DI_E * E + e];
+    if (o->dissipation) o->dissipation[e] = inst[DI_EPS * E + e];
+    if (o->power) o->power[e] = inst[DI_PI * E + e];
+    if (o->flux) o->flux[e] = inst[DI_Q * E + e];
+    if (o->tau_lower) o->tau_lower[e] = inst[DI_TLO * E + e];
+    if (o->tau_upper) o->tau_upper[e] = inst[DI_THI * E + e];
+    if (o->gamma) o->gamma[e] = gam[e];
+    if (o->div_max) {
+      double d;
+      std::memcpy(&d, &dm[e], sizeof(double));
+      o->div_max[e] = d;
+    }
+    if (o->failed) o->failed[e] = fl[e];
+    anyf |= fl[e];
+  }
+  o->samples = h->samples;
+  o->steps = h->steps;
+  if (h->samples > 0) {
+    const double inv = 1.0 / (double(h->samples) * E);
+    for (int j = 0; j < My; ++j) {
+      double s[NPA] = {0};
+      for (int q = 0; q < NPA; ++q)
+        for (int e = 0; e < E; ++e) s[q] += acc[(size_t(q) * My + j) * E + e];
+      for (int q = 0; q < NPA; ++q) s[q] *= inv;
+      const double U = s[PA_U], W = s[PA_W];
+      if (o->U) o->U[j] = U;
+      if (o->W) o->W[j] = W;
+      if (o->urms) o->urms[j] = std::sqrt(std::fmax(s[PA_UU] - U * U, 0.0));
+      if (o->vrms) o->vrms[j] = std::sqrt(std::fmax(s[PA_VV], 0.0));
+      if (o->wrms) o->wrms[j] = std::sqrt(std::fmax(s[PA_WW] - W * W, 0.0));
+      if (o->uv) o->uv[j] = s[PA_UV];
+    }
+    double lo = 0, hi = 0;
+    for (int e = 0; e < E; ++e) {
+      lo += acc[size_t(NPA) * My * E + e];
+      hi += acc[size_t(NPA) * My * E + E + e];
+    }
+    lo *= inv;
+    hi *= inv;
+    o->tau_w = h->flow == DNS_FLOW_COUETTE ? 0.5 * (std::fabs(lo) + std::fabs(hi)) / h->Re
+                                           : (lo - hi) / (2.0 * h->Re);
+    o->re_tau = h->Re * std::sqrt(std::fabs(o->tau_w));
+  } else {
+    o->tau_w = 0.0;
+    o->re_tau = 0.0;
+  }
+  if (anyf) return fail(h, DNS_E_NONFINITE, "a member produced a non-finite value");
+  return DNS_OK;
+}
+
+int dns_stats_reset(dns_handle* h) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  HIP_OR_FAIL(h, hipMemsetAsync(h->acc, 0, (size_t(NPA) * h->My * h->E + 2 * h->E) * sizeof(double), h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  h->samples = 0;
+  return DNS_OK;
+}
+
+void dns_destroy(dns_handle* h) {
+  if (!h) return;
+  hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+}
+
+const char* dns_last_error(const dns_handle* h) {
+  return h ? h->err.c_str() : g_thread_err.c_str();
+}
+
+int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  int rc = refresh_velocities(h);
+  if (rc) return rc;
+  HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  const int E = h->E, My = h->My, K = h->K;
+  const size_t vt = vt_size(h->precision);
+  auto fetch = [&](const void* src, int nf, double* dst) -> int {
+    const size_t n = size_t(nf) * My * K * E * 2;
+    std::vector<unsigned char> raw(n * vt);
+    if (hipMemcpy(raw.data(), src, raw.size(), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    for (int f = 0; f < nf; ++f)
+      for (int e = 0; e < E; ++e)
+        for (int j = 0; j < My; ++j)
+          for (int m = 0; m < K; ++m) {
+            const size_t d = (((size_t(f) * My + j) * K + m) * E + e) * 2;
+            const size_t o = (((size_t(f) * E + e) * My + j) * K + m) * 2;
+            for (int c = 0; c < 2; ++c)
+              dst[o + c] = vt == 8 ? reinterpret_cast<const double*>(raw.data())[d + c]
+                                   : double(reinterpret_cast<const float*>(raw.data())[d + c]);
+          }
+    return 0;
+  };
+  if (vel && fetch(h->vel, 5, vel)) return fail(h, DNS_E_HIP, "copying velocity fields");
+  if (nl && fetch(h->nl, 3, nl)) return fail(h, DNS_E_HIP, "copying advection fields");
+  if (means) {
+    std::vector<double> mm(size_t(2) * My * E);
+    HIP_OR_FAIL(h, hipMemcpy(mm.data(), h->means, mm.size() * 8, hipMemcpyDeviceToHost));
+    for (int q = 0; q < 2; ++q)
+      for (int e = 0; e < E; ++e)
+        for (int j = 0; j < My; ++j) means[(size_t(q) * E + e) * My + j] = mm[(size_t(q) * My + j) * E + e];
+  }
+  return DNS_OK;
+}
+
+int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  if (nreps < 1) return fail(h, DNS_E_INVALID, "nreps must be >= 1");
+  if (!h->vel_fresh) {
+    int rc = refresh_velocities(h);
+    if (rc) return rc;
+  }
+  hipEvent_t e0, e1, e2;
+  HIP_OR_FAIL(h, hipEventCreate(&e0));
+  HIP_OR_FAIL(h, hipEventCreate(&e1));
+  HIP_OR_FAIL(h, hipEventCreate(&e2));
+  // one untimed launch of each, then nreps timed launches of each
+  HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
+  HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, 1), h->stream));
+  HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
+  for (int r = 0; r < nreps; ++r)
+    HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
+  HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
+  for (int r = 0; r < nreps; ++r) HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, 1), h->stream));
+  HIP_OR_FAIL(h, hipEventRecord(e2, h->stream));
+  HIP_OR_FAIL(h, hipEventSynchronize(e2));
+  float t01 = 0.f, t12 = 0.f;
+  HIP_OR_FAIL(h, hipEventElapsedTime(&t01, e0, e1));
+  HIP_OR_FAIL(h, hipEventElapsedTime(&t12, e1, e2));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipEventDestroy(e2);
+  if (plane_ms) *plane_ms = double(t01) / nreps;
+  if (mode_ms) *mode_ms = double(t12) / nreps;
+  // the mode kernel rewrote the stage buffers from sub-step-1 data
+  h->vel_fresh = false;
+  return DNS_OK;
+}
+
+int dns_host_operators(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, double dt,
+                       int h_index, double* ops, double* mean_ops, double* lift, double* green,
+                       double* D1, double* D1c, double* ccw) {
+  if (!g || !(g->Lx > 0) || !(g->Lz > 0) || !(Re > 0) || !(dt > 0) || (h_index != 0 && h_index != 1))
+    return fail(nullptr, DNS_E_INVALID, "invalid operator request");
+  if (Nx <= 0 || Nz <= 0 || (Nx % 2) || (Nz % 2) || Ny < 5 || Ny > 257)
+    return fail(nullptr, DNS_E_INVALID, "invalid grid");
+  const double Uw = g->Uw > 0 ? g->Uw : 1.0;
+  const double Ub = g->flow == DNS_FLOW_COUETTE ? -Uw : 0.0;
+  const double Ut = g->flow == DNS_FLOW_COUETTE ? Uw : 0.0;
+  HostOperators ho;
+  if (build_operators(Ny, Nx / 2, Nz / 2, 2.0 * M_PI / g->Lx, 2.0 * M_PI / g->Lz, Re, dt, Ub, Ut, &ho))
+    return fail(nullptr, DNS_E_INVALID, "a Crank-Nicolson operator is singular");
+  auto put = [](double* dst, const std::vector<double>& src) {
+    if (dst) std::memcpy(dst, src.data(), src.size() * sizeof(double));
+  };
+  put(ops, ho.ops[h_index]);
+  put(mean_ops, ho.mean_ops[h_index]);
+  put(lift, ho.lift[h_index]);
+  put(green, ho.green[h_index]);
+  put(D1, ho.D1);
+  put(D1c, ho.D1c);
+  put(ccw, ho.ccw);
+  return DNS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal interfaces between the host orchestration (dns_api.cpp), the host
+// operator builder (operators.cpp) and the HIP kernels.
+//
+// Device layouts (members innermost, "E" = ensemble size):
+//   state v, eta   : complex double [K][N][E]       K = Nx/2 * (Nz-1) modes
+//   state U, W     : double         [My][E]         walls included
+//   vel            : complex VT     [5][My][K][E]   u, v, w, du/dy, dw/dy
+//   nl             : complex VT     [3][My][K][E]   advection N_u, N_v, N_w
+//   means          : double         [2][My][E]      <uv>, <wv>
+//   psum           : double         [NPS][My][E]    plane means for statistics
+//   hist F, G      : complex double [K][N][E]       RK3 forcing history
+//   hist EU, EW    : double         [N][E]
+//   ops            : double [2 h][G][4][N][N]       A_v, B_v, A_eta, B_eta
+// Mode index m = nx*(Nz-1) + iz with iz in FFT order; operator group
+// g = nx*(Nz/2) + |nz| holds the modes (nx, +nz) and (nx, -nz).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+namespace dns {
+
+enum PlaneSum { PS_UU = 0, PS_VV = 1, PS_WW = 2, PS_GRAD = 3, NPS = 4 };
+
+struct PlaneArgs {
+  const void* vel;
+  void* nl;
+  double* means;
+  double* psum;   // nullptr: skip statistics sums
+  int My, K, E;
+  double kxs, kzs;  // 2 pi / Lx, 2 pi / Lz
+};
+
+struct ModeArgs {
+  // state (FP64)
+  double* v;     // complex [K][N][E]
+  double* eta;   // complex [K][N][E]
+  double* U;     // [My][E]
+  double* W;
+  // RK3 history (FP64)
+  double* hF;
+  double* hG;
+  double* hEU;   // [N][E]
+  double* hEW;
+  // pseudo-spectral stage buffers
+  void* vel;          // complex VT [5][My][K][E] (written)
+  const void* nl;     // complex VT [3][My][K][E] (read)
+  const double* means;  // [2][My][E]
+  // operators
+  const double* ops;    // [G][4][N][N] for this h
+  const double* mean_ops;  // [2 (A_U, B_U)][N][N] for this h
+  const double* lift;   // [N]
+  const double* green;  // [N]
+  const double* D1;     // [My][My]
+  const double* D1c;    // [My][N]
+  const double* ccw;    // [My] Clenshaw-Curtis weights
+  // per-member outputs
+  double* gamma;        // [E]
+  int* failed;          // [E]
+  unsigned long long* divmax;  // [E] (bit pattern of a non-negative double)
+  // sizes and parameters
+  int My, N, K, E, L, P, NZ, G, ET, ntiles;
+  double kxs, kzs, hdt, Ubot, Utop, Qtarget;
+  int stage;      // 0, 1, 2: sub-step index; -1: velocities of the state only
+  int poiseuille;
+};
+
+// Kernel launchers (kernels_*.hip).  Return hipSuccess or the launch error.
+hipError_t launch_plane(int precision, int Nx, int Nz, const PlaneArgs& a, hipStream_t s);
+bool plane_supported(int Nx, int Nz);
+hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
+int mode_member_tile(int My, int E);
+
+// layout transposes between the host state layout and the device layout
+hipError_t launch_state_to_device(const double* host_layout_dev, double* dev, int E0, int count,
+                                  int E, int K, int N, hipStream_t s);
+hipError_t launch_state_from_device(const double* dev, double* host_layout_dev, int E0, int count,
+                                    int E, int K, int N, hipStream_t s);
+hipError_t launch_profile_to_device(const double* host_layout_dev, double* dev, int E0, int count,
+                                    int E, int My, hipStream_t s);
+hipError_t launch_profile_from_device(const double* dev, double* host_layout_dev, int E0, int count,
+                                      int E, int My, hipStream_t s);
+
+struct StatsArgs {
+  const double* psum;    // [NPS][My][E]
+  const double* means;   // [2][My][E]
+  const double* U;       // [My][E]
+  const double* W;
+  const double* ccw;     // [My]
+  const double* D1;      // [My][My]
+  const double* gamma;   // [E]
+  double* acc;           // [NPA][My][E] time sums, then [2][E] wall shear sums
+  double* inst;          // [NDI][E] instantaneous per-member diagnostics
+  int* failed;           // [E] sticky non-finite flag
+  int My, E;
+  double Re, Uw, poiseuille, Qtarget;
+};
+enum ProfileAcc { PA_U = 0, PA_W, PA_U2, PA_W2, PA_UU, PA_VV, PA_WW, PA_UV, NPA };
+enum InstDiag { DI_E = 0, DI_EPS, DI_PI, DI_Q, DI_TLO, DI_THI, NDI };
+hipError_t launch_stats(const StatsArgs& a, int accumulate, hipStream_t s);
+
+// Host operator builder (operators.cpp), long double internally.
+struct HostOperators {
+  int My = 0, N = 0, G = 0;
+  std::vector<double> D1;      // My*My
+  std::vector<double> D1c;     // My*N
+  std::vector<double> ccw;     // My
+  std::vector<double> ops[2];  // per h: G*4*N*N
+  std::vector<double> mean_ops[2];  // per h: 2*N*N
+  std::vector<double> lift[2];      // per h: N
+  std::vector<double> green[2];     // per h: N
+  double max_cond = 0.0;
+};
+// h index 0 is h = 1/2, index 1 is h = 1.
+int build_operators(int My, int L, int P, double kxs, double kzs, double Re, double dt,
+                    double Ubot, double Utop, HostOperators* out);
+
+}  // namespace dns

@@ -1,0 +1,156 @@
+// Layout transposes between the host state layout and the member-innermost
+// device layout, and the per-step diagnostics / one-point statistics kernel.
+//
+// Statistics follow Sec. 4 of the paper (one-point statistics: mean profile,
+// rms fluctuations about it, tangential Reynolds stress); energy, dissipation
+// and power input follow from the momentum equation between walls (Sec. 2).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace dns {
+
+namespace {
+
+// host layout [mem][m][j] (complex) <-> device [m][j][e] (complex)
+__global__ void state_to_device(const double* __restrict__ src, double* __restrict__ dst, int E0,
+                                int count, int E, int K, int N) {
+  const size_t total = size_t(count) * K * N;
+  for (size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x; idx < total;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    const int jj = int(idx % N);
+    const size_t t = idx / N;
+    const int m = int(t % K);
+    const int mem = int(t / K);
+    const size_t d = (size_t(m) * N + jj) * E + (E0 + mem);
+    dst[2 * d] = src[2 * idx];
+    dst[2 * d + 1] = src[2 * idx + 1];
+  }
+}
+
+__global__ void state_from_device(const double* __restrict__ src, double* __restrict__ dst, int E0,
+                                  int count, int E, int K, int N) {
+  const size_t total = size_t(count) * K * N;
+  for (size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x; idx < total;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    const int jj = int(idx % N);
+    const size_t t = idx / N;
+    const int m = int(t % K);
+    const int mem = int(t / K);
+    const size_t d = (size_t(m) * N + jj) * E + (E0 + mem);
+    dst[2 * idx] = src[2 * d];
+    dst[2 * idx + 1] = src[2 * d + 1];
+  }
+}
+
+// host [mem][j] <-> device [j][e]
+__global__ void profile_to_device(const double* __restrict__ src, double* __restrict__ dst, int E0,
+                                  int count, int E, int My) {
+  const int total = count * My;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int j = idx % My, mem = idx / My;
+    dst[size_t(j) * E + E0 + mem] = src[idx];
+  }
+}
+
+__global__ void profile_from_device(const double* __restrict__ src, double* __restrict__ dst, int E0,
+                                    int count, int E, int My) {
+  const int total = count * My;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int j = idx % My, mem = idx / My;
+    dst[idx] = src[size_t(j) * E + E0 + mem];
+  }
+}
+
+int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 65535) b = 65535;
+  return int(b);
+}
+
+// One thread per member: volume integrals with Clenshaw-Curtis weights
+// (fixed summation order), wall shear, power input, finiteness, and the
+// optional time accumulation of the plane profiles.
+__global__ void stats_kernel(StatsArgs a, int accumulate) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.E) return;
+  const int My = a.My, E = a.E;
+  double en = 0.0, ds = 0.0, q = 0.0, dlo = 0.0, dhi = 0.0;
+  for (int j = 0; j < My; ++j) {
+    const size_t je = size_t(j) * E + e;
+    const double w = a.ccw[j];
+    en += w * (a.psum[size_t(PS_UU) * My * E + je] + a.psum[size_t(PS_VV) * My * E + je] +
+               a.psum[size_t(PS_WW) * My * E + je]);
+    ds += w * a.psum[size_t(PS_GRAD) * My * E + je];
+    q += w * a.U[je];
+    dlo += a.D1[j] * a.U[je];
+    dhi += a.D1[size_t(My - 1) * My + j] * a.U[je];
+  }
+  const double Ly = 2.0;
+  en = 0.5 * en / Ly;
+  ds = ds / (a.Re * Ly);
+  const double pin = a.poiseuille != 0.0 ? a.gamma[e] * q / Ly : a.Uw * (dhi + dlo) / (a.Re * Ly);
+  double* inst = a.inst;
+  inst[DI_E * E + e] = en;
+  inst[DI_EPS * E + e] = ds;
+  inst[DI_PI * E + e] = pin;
+  inst[DI_Q * E + e] = q;
+  inst[DI_TLO * E + e] = dlo / a.Re;
+  inst[DI_THI * E + e] = dhi / a.Re;
+  if (!isfinite(en) || !isfinite(ds) || !isfinite(q)) a.failed[e] = 1;
+  if (accumulate) {
+    for (int j = 0; j < My; ++j) {
+      const size_t je = size_t(j) * E + e;
+      const double U = a.U[je], W = a.W[je];
+      a.acc[size_t(PA_U) * My * E + je] += U;
+      a.acc[size_t(PA_W) * My * E + je] += W;
+      a.acc[size_t(PA_U2) * My * E + je] += U * U;
+      a.acc[size_t(PA_W2) * My * E + je] += W * W;
+      a.acc[size_t(PA_UU) * My * E + je] += a.psum[size_t(PS_UU) * My * E + je];
+      a.acc[size_t(PA_VV) * My * E + je] += a.psum[size_t(PS_VV) * My * E + je];
+      a.acc[size_t(PA_WW) * My * E + je] += a.psum[size_t(PS_WW) * My * E + je];
+      a.acc[size_t(PA_UV) * My * E + je] += a.means[je];
+    }
+    // wall shear for tau_w: accumulate in the extra slot after the profiles
+    a.acc[size_t(NPA) * My * E + e] += dlo;
+    a.acc[size_t(NPA) * My * E + E + e] += dhi;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_state_to_device(const double* src, double* dst, int E0, int count, int E, int K,
+                                  int N, hipStream_t s) {
+  hipLaunchKernelGGL(state_to_device, dim3(grid_for(size_t(count) * K * N)), dim3(256), 0, s, src,
+                     dst, E0, count, E, K, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_from_device(const double* src, double* dst, int E0, int count, int E, int K,
+                                    int N, hipStream_t s) {
+  hipLaunchKernelGGL(state_from_device, dim3(grid_for(size_t(count) * K * N)), dim3(256), 0, s,
+                     src, dst, E0, count, E, K, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_profile_to_device(const double* src, double* dst, int E0, int count, int E,
+                                    int My, hipStream_t s) {
+  hipLaunchKernelGGL(profile_to_device, dim3(grid_for(size_t(count) * My)), dim3(256), 0, s, src,
+                     dst, E0, count, E, My);
+  return hipGetLastError();
+}
+
+hipError_t launch_profile_from_device(const double* src, double* dst, int E0, int count, int E,
+                                      int My, hipStream_t s) {
+  hipLaunchKernelGGL(profile_from_device, dim3(grid_for(size_t(count) * My)), dim3(256), 0, s,
+                     src, dst, E0, count, E, My);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const StatsArgs& a, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(stats_kernel, dim3((a.E + 63) / 64), dim3(64), 0, s, a, accumulate);
+  return hipGetLastError();
+}
+
+}  // namespace dns

@@ -1,0 +1,371 @@
+// Pseudo-spectral advection stage: one workgroup per (Chebyshev plane j, member e).
+//
+// Paper Sec. 3.1-3.2: the advection term u . grad u_i is formed pointwise on a
+// 3/2-padded physical grid (2/3-rule dealiasing), its x-z transform truncated
+// back to the kept modes; the mean-flow equations need the plane means <uv>
+// and <wv> (Eqs. (U00), (W00)).
+//
+// Inputs per (j, e): spectral u, v, w, du/dy, dw/dy (the derivative fields
+// d/dx = i kx, d/dz = i kz are formed on the fly; dv/dy = -(du/dx + dw/dz) by
+// continuity, exact at every node).  The physical plane (Mz x Mx) is processed
+// in R chunks of PP rows z_p, p = R q + r: a chunk's rows are the output of a
+// PP-point inverse FFT of the Mz-point column folded onto PP points with
+// twiddles e^{2 pi i n r / Mz}.  Each chunk does
+//   Z1 z-iFFT(u, v, w) -> X1 x-iFFT(u, v, w) -> phys u, v, w
+//   XA x-iFFT(ux, vx, wx)      -> Nu = u ux, Nv = u vx, Nw = u wx, VY = -ux
+//   Z2 z-iFFT(uz, vz, wz) -> XB -> Nu += w uz, Nv += w vz, Nw += w wz, VY -= wz
+//   Z3 z-iFFT(uy, wy)     -> XC -> Nu += v uy, Nw += v wy
+//   P  Nv += v VY, plane sums
+//   XF x-FFT(Nu, Nv, Nw) -> ZF z-FFT of the chunk -> accumulate
+//      N_hat(nz) += e^{-2 pi i r nz / Mz} Y_r[nz mod PP] in registers.
+// Pairs of physical rows share one complex x transform (real + i imag).
+#include <type_traits>
+
+#include "fft.h"
+#include "internal.h"
+
+namespace dns {
+
+namespace {
+
+// Spread consecutive logical block indices over one XCD: hardware dispatches
+// block b to XCD b % 8, so logical neighbours (same plane, adjacent members,
+// which share cache lines of the member-innermost layout) land on one L2.
+__device__ __forceinline__ int xcd_logical(int b, int nblk) {
+  const int q = nblk >> 3, rem = nblk & 7;
+  const int x = b & 7, local = b >> 3;
+  return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
+}
+
+template <typename VT>
+struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename T, typename VT>
+__device__ __forceinline__ cx<T> ldc(const VT* p) {
+  using V = typename Vec2<VT>::type;
+  const V v = *reinterpret_cast<const V*>(p);
+  return cx<T>{T(v.x), T(v.y)};
+}
+
+template <typename T, typename VT>
+__device__ __forceinline__ void stc(VT* p, cx<T> c) {
+  using V = typename Vec2<VT>::type;
+  V v;
+  v.x = VT(c.x);
+  v.y = VT(c.y);
+  *reinterpret_cast<V*>(p) = v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+constexpr int kNT = 256;
+
+template <typename T, int L, int P, int PP>
+struct PlaneCfg {
+  static constexpr int MX = 3 * L, MZ = 3 * P, NZ = 2 * P - 1;
+  static constexpr int R = MZ / PP, PH = PP / 2;
+  static constexpr int ZB = 3 * L * PP;                       // complex elements
+  static constexpr int MIDZ = 3 * L * PP, MIDX = 3 * PH * MX;
+  static constexpr int MID = MIDZ > MIDX ? MIDZ : MIDX;
+  static constexpr int NPT = PP * MX;                          // physical points per chunk
+  static constexpr int NACC = (3 * L * NZ + kNT - 1) / kNT;
+  static_assert(MZ % PP == 0 && PP % 2 == 0, "chunk rows must divide Mz and pair up");
+};
+
+enum Phys { PU = 0, PV, PW, PNU, PNV, PNW, PVY, NPHYS };
+
+}  // namespace
+
+template <typename T, typename VT, int L, int P, int PP>
+__global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
+  using C = cx<T>;
+  using Cfg = PlaneCfg<T, L, P, PP>;
+  constexpr int MX = Cfg::MX, MZ = Cfg::MZ, NZ = Cfg::NZ, R = Cfg::R, PH = Cfg::PH;
+  __shared__ C rootX[MX];
+  __shared__ C rootZ[MZ];
+  __shared__ C rootP[PP];
+  __shared__ C zb[Cfg::ZB];
+  __shared__ C mid[Cfg::MID];
+  __shared__ T phys[NPHYS][Cfg::NPT];
+  __shared__ double red[8][kNT / 64];
+
+  const int tid = threadIdx.x;
+  const int flat = xcd_logical(blockIdx.x, gridDim.x);
+  const int E = a.E, K = a.K, My = a.My;
+  const int j = flat / E, e = flat - j * E;
+  const VT* vel = static_cast<const VT*>(a.vel);
+  const bool want_stats = a.psum != nullptr;
+  const T kxs = T(a.kxs), kzs = T(a.kzs);
+
+  for (int t = tid; t < MX; t += kNT) {
+    T s, c;
+    if constexpr (sizeof(T) == 8) sincospi(-2.0 * t / MX, &s, &c); else sincospif(-2.0f * t / MX, &s, &c);
+    rootX[t] = C{c, s};
+  }
+  for (int t = tid; t < MZ; t += kNT) {
+    T s, c;
+    if constexpr (sizeof(T) == 8) sincospi(-2.0 * t / MZ, &s, &c); else sincospif(-2.0f * t / MZ, &s, &c);
+    rootZ[t] = C{c, s};
+  }
+  __syncthreads();
+  for (int t = tid; t < PP; t += kNT) rootP[t] = rootZ[t * R];
+  __syncthreads();
+
+  // spectral input element (field f, nx, iz) of this (j, e), as complex T
+  auto vel_at = [&](int f, int nx, int iz) -> C {
+    const size_t off = ((size_t(f) * My + j) * K + size_t(nx) * NZ + iz) * E + e;
+    return ldc<T>(vel + 2 * off);
+  };
+
+  // register accumulators of the forward transform: flat (f, nx, iz)
+  C acc[Cfg::NACC];
+#pragma unroll
+  for (int k = 0; k < Cfg::NACC; ++k) acc[k] = C{T(0), T(0)};
+  double s_uv = 0.0, s_wv = 0.0, s_uu = 0.0, s_vv = 0.0, s_ww = 0.0, s_grad = 0.0;
+
+  for (int r = 0; r < R; ++r) {
+    // ---- z inverse of NF spectral fields into zb[fi][nx][q] ----------------
+    auto zinv = [&](auto nf_tag, int fbase, bool dz) {
+      constexpr int NF = decltype(nf_tag)::value;
+      auto load = [&](int b, int np) -> C {
+        const int fi = b / L, nx = b - fi * L;
+        C s{T(0), T(0)};
+#pragma unroll
+        for (int fold = 0; fold < R; ++fold) {
+          const int n = np + PP * fold;
+          int nz;
+          if (n < P) nz = n;
+          else if (n > MZ - P) nz = n - MZ;
+          else continue;
+          C x = vel_at(fbase + fi, nx, nz >= 0 ? nz : nz + NZ);
+          if (dz) x = cmuli<1>(cscale(x, kzs * T(nz)));
+          const int t = (n * r) % MZ;
+          s = cadd(s, cmul(x, cconj(rootZ[t])));
+        }
+        return s;
+      };
+      auto store = [&](int b, int q, C v) { zb[b * PP + q] = v; };
+      fft2pass<T, PP, +1, NF * L, kNT>(mid, rootP, load, store);
+    };
+    // ---- x inverse of NF fields held in zb, rows paired (q, q + PH) -------
+    auto xinv = [&](auto nf_tag, bool dx, auto action) {
+      constexpr int NF = decltype(nf_tag)::value;
+      auto load = [&](int b, int n) -> C {
+        const int fi = b / PH, qp = b - fi * PH;
+        const C* col = zb + fi * L * PP;
+        auto cval = [&](int nx, int q) -> C {
+          C c = col[nx * PP + q];
+          if (dx) c = cmuli<1>(cscale(c, kxs * T(nx)));
+          return c;
+        };
+        if (n == 0) {
+          if (dx) return C{T(0), T(0)};
+          return C{col[qp].x, col[PH + qp].x};
+        }
+        if (n < L) {
+          const C c0 = cval(n, qp), c1 = cval(n, qp + PH);
+          return C{c0.x - c1.y, c0.y + c1.x};
+        }
+        if (n > MX - L) {
+          const C c0 = cconj(cval(MX - n, qp)), c1 = cconj(cval(MX - n, qp + PH));
+          return C{c0.x - c1.y, c0.y + c1.x};
+        }
+        return C{T(0), T(0)};
+      };
+      auto store = [&](int b, int n, C v) {
+        const int fi = b / PH, qp = b - fi * PH;
+        action(fi, qp * MX + n, v.x);
+        action(fi, (qp + PH) * MX + n, v.y);
+      };
+      fft2pass<T, MX, +1, NF * PH, kNT>(mid, rootX, load, store);
+    };
+    std::integral_constant<int, 3> three;
+    std::integral_constant<int, 2> two;
+
+    zinv(three, 0, false);
+    __syncthreads();
+    xinv(three, false, [&](int fi, int p, T val) { phys[PU + fi][p] = val; });
+    __syncthreads();
+    xinv(three, true, [&](int fi, int p, T val) {
+      const T u = phys[PU][p];
+      if (fi == 0) {
+        phys[PNU][p] = u * val;
+        phys[PVY][p] = -val;
+      } else if (fi == 1) {
+        phys[PNV][p] = u * val;
+      } else {
+        phys[PNW][p] = u * val;
+      }
+      if (want_stats) s_grad += double(val) * double(val);
+    });
+    __syncthreads();
+    zinv(three, 0, true);
+    __syncthreads();
+    xinv(three, false, [&](int fi, int p, T val) {
+      const T w = phys[PW][p];
+      if (fi == 0) {
+        phys[PNU][p] += w * val;
+      } else if (fi == 1) {
+        phys[PNV][p] += w * val;
+      } else {
+        phys[PNW][p] += w * val;
+        phys[PVY][p] -= val;
+      }
+      if (want_stats) s_grad += double(val) * double(val);
+    });
+    __syncthreads();
+    zinv(two, 3, false);
+    __syncthreads();
+    xinv(two, false, [&](int fi, int p, T val) {
+      const T v = phys[PV][p];
+      if (fi == 0) phys[PNU][p] += v * val; else phys[PNW][p] += v * val;
+      if (want_stats) s_grad += double(val) * double(val);
+    });
+    __syncthreads();
+    for (int p = tid; p < Cfg::NPT; p += kNT) {
+      const T u = phys[PU][p], v = phys[PV][p], w = phys[PW][p], vy = phys[PVY][p];
+      phys[PNV][p] += v * vy;
+      s_uv += double(u) * double(v);
+      s_wv += double(w) * double(v);
+      if (want_stats) {
+        s_uu += double(u) * double(u);
+        s_vv += double(v) * double(v);
+        s_ww += double(w) * double(w);
+        s_grad += double(vy) * double(vy);
+      }
+    }
+    __syncthreads();
+    // ---- forward x transform of (Nu, Nv, Nw); keep |kx| < L ----------------
+    {
+      auto load = [&](int b, int n) -> C {
+        const int f = b / PH, qp = b - f * PH;
+        return C{phys[PNU + f][qp * MX + n], phys[PNU + f][(qp + PH) * MX + n]};
+      };
+      auto store = [&](int b, int k, C v) {
+        if (k < L) zb[b * 2 * L + k] = v;
+        else if (k > MX - L) zb[b * 2 * L + k - MX + 2 * L] = v;
+      };
+      fft2pass<T, MX, -1, 3 * PH, kNT>(mid, rootX, load, store);
+    }
+    __syncthreads();
+    // ---- forward z transform of the chunk (unpacking the row pairs) ------------
+    {
+      auto load = [&](int b, int q) -> C {
+        const int f = b / L, nx = b - f * L;
+        const int qp = q < PH ? q : q - PH;
+        const C* row = zb + (f * PH + qp) * 2 * L;
+        const C zk = row[nx];
+        const C zm = cconj(row[nx == 0 ? 0 : 2 * L - nx]);
+        if (q < PH) return C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
+        // (zk - zm) / (2 i)
+        return C{T(0.5) * (zk.y - zm.y), T(-0.5) * (zk.x - zm.x)};
+      };
+      // Y is written to zb after pass 1 has consumed it (pass 2 reads only mid)
+      auto storeY = [&](int b, int k, C v) { zb[b * PP + k] = v; };
+      fft2pass<T, PP, -1, 3 * L, kNT>(mid, rootP, load, storeY);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < Cfg::NACC; ++k) {
+      const int idx = tid + k * kNT;
+      if (idx < 3 * L * NZ) {
+        const int f = idx / (L * NZ);
+        const int rem = idx - f * L * NZ;
+        const int nx = rem / NZ, iz = rem - nx * NZ;
+        const int nz = iz < P ? iz : iz - NZ;
+        const int kk = ((nz % PP) + PP) % PP;
+        const int t = (((r * nz) % MZ) + MZ) % MZ;
+        acc[k] = cadd(acc[k], cmul(zb[(f * L + nx) * PP + kk], rootZ[t]));
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write the truncated advection spectrum --------------------------------
+  VT* nl = static_cast<VT*>(a.nl);
+  const T inv = T(1.0 / (double(MX) * double(MZ)));
+#pragma unroll
+  for (int k = 0; k < Cfg::NACC; ++k) {
+    const int idx = tid + k * kNT;
+    if (idx < 3 * L * NZ) {
+      const int f = idx / (L * NZ);
+      const int m = idx - f * L * NZ;
+      const size_t off = ((size_t(f) * My + j) * K + m) * E + e;
+      stc<T>(nl + 2 * off, cscale(acc[k], inv));
+    }
+  }
+
+  // ---- plane means (fixed-order reductions) -------------------------------------
+  const double vals[6] = {s_uv, s_wv, s_uu, s_vv, s_ww, s_grad};
+  const int nq = want_stats ? 6 : 2;
+  const int lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+  for (int qi = 0; qi < 6; ++qi) {
+    if (qi < nq) {
+      const double sred = wave_sum(vals[qi]);
+      if (lane == 0) red[qi][wv] = sred;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double norm = 1.0 / (double(MX) * double(MZ));
+    double tot[6];
+    for (int qi = 0; qi < nq; ++qi) {
+      double s = 0.0;
+      for (int w = 0; w < kNT / 64; ++w) s += red[qi][w];
+      tot[qi] = s * norm;
+    }
+    a.means[(size_t(0) * My + j) * E + e] = tot[0];
+    a.means[(size_t(1) * My + j) * E + e] = tot[1];
+    if (want_stats) {
+      a.psum[(size_t(PS_UU) * My + j) * E + e] = tot[2];
+      a.psum[(size_t(PS_VV) * My + j) * E + e] = tot[3];
+      a.psum[(size_t(PS_WW) * My + j) * E + e] = tot[4];
+      a.psum[(size_t(PS_GRAD) * My + j) * E + e] = tot[5];
+    }
+  }
+}
+
+namespace {
+
+template <typename T, typename VT, int L, int P, int PP>
+hipError_t run_plane(const PlaneArgs& a, hipStream_t s) {
+  const int nblk = a.My * a.E;
+  hipLaunchKernelGGL((plane_kernel<T, VT, L, P, PP>), dim3(nblk), dim3(kNT), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool plane_supported(int Nx, int Nz) {
+  return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64);
+}
+
+// precision 0: FP64 storage and arithmetic; 1/2: FP32 storage and FFT arithmetic.
+hipError_t launch_plane(int precision, int Nx, int Nz, const PlaneArgs& a, hipStream_t s) {
+  if (!plane_supported(Nx, Nz)) return hipErrorInvalidValue;
+  if (precision == 0) {
+    switch (Nx) {
+      case 16: return run_plane<double, double, 8, 8, 24>(a, s);
+      case 32: return run_plane<double, double, 16, 16, 16>(a, s);
+      case 48: return run_plane<double, double, 24, 24, 12>(a, s);
+      case 64: return run_plane<double, double, 32, 32, 16>(a, s);
+    }
+  } else {
+    switch (Nx) {
+      case 16: return run_plane<float, float, 8, 8, 24>(a, s);
+      case 32: return run_plane<float, float, 16, 16, 16>(a, s);
+      case 48: return run_plane<float, float, 24, 24, 12>(a, s);
+      case 64: return run_plane<float, float, 32, 32, 16>(a, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dns

@@ -1,0 +1,252 @@
+"""ctypes binding of libdns_ensemble.so (the C ABI declared in include/dns.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Host arrays are numpy; device arrays may be torch CUDA tensors (their
+``data_ptr()`` is passed with ``on_device=1``).  There is no CPU fallback:
+opening the library fails loudly when it is missing or was built for another
+machine.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdns_ensemble.so")
+
+DNS_OK = 0
+DNS_E_INVALID = -1
+DNS_E_NOMEM = -2
+DNS_E_HIP = -3
+DNS_E_NONFINITE = -4
+DNS_E_UNSUPPORTED = -5
+DNS_E_STATE = -6
+
+COUETTE = 0
+POISEUILLE = 1
+
+OPT_PRECISION = 1
+OPT_STREAM = 2
+OPT_GRAPH = 3
+OPT_STATS = 4
+
+PREC_FP64 = 0
+PREC_MIXED_FP32 = 1
+
+EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "dns_step",
+            "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",
+            "dns_debug_stage0", "dns_kernel_times", "dns_host_operators"]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("flow", ctypes.c_int), ("Lx", ctypes.c_double), ("Lz", ctypes.c_double),
+                ("Uw", ctypes.c_double), ("flux", ctypes.c_double)]
+
+
+class StateView(ctypes.Structure):
+    _fields_ = [("v_hat", ctypes.c_void_p), ("eta_hat", ctypes.c_void_p),
+                ("U00", ctypes.c_void_p), ("W00", ctypes.c_void_p), ("on_device", ctypes.c_int)]
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+
+class StatsOut(ctypes.Structure):
+    _fields_ = [("energy", _DP), ("dissipation", _DP), ("power", _DP), ("flux", _DP),
+                ("gamma", _DP), ("div_max", _DP), ("tau_lower", _DP), ("tau_upper", _DP),
+                ("failed", _IP), ("U", _DP), ("W", _DP), ("urms", _DP), ("vrms", _DP),
+                ("wrms", _DP), ("uv", _DP), ("tau_w", ctypes.c_double),
+                ("re_tau", ctypes.c_double), ("samples", ctypes.c_longlong),
+                ("steps", ctypes.c_longlong)]
+
+
+_lib = None
+
+
+def library(path=LIB_PATH):
+    """Open the HIP library (once).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2306_12739_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.dns_create.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(vp)]
+    lib.dns_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
+    lib.dns_set_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(StateView)]
+    lib.dns_get_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(StateView)]
+    lib.dns_step.argtypes = [vp, ctypes.c_int]
+    lib.dns_stats.argtypes = [vp, ctypes.POINTER(StatsOut)]
+    lib.dns_stats_reset.argtypes = [vp]
+    lib.dns_sync.argtypes = [vp]
+    lib.dns_destroy.argtypes = [vp]
+    lib.dns_destroy.restype = None
+    lib.dns_last_error.argtypes = [vp]
+    lib.dns_last_error.restype = ctypes.c_char_p
+    lib.dns_debug_stage0.argtypes = [vp, _DP, _DP, _DP]
+    lib.dns_kernel_times.argtypes = [vp, ctypes.c_int, _DP, _DP]
+    lib.dns_host_operators.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                       _DP, _DP, _DP, _DP, _DP, _DP, _DP]
+    for name in EXPORTED:
+        if name not in ("dns_destroy", "dns_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, h_index, Uw=1.0):
+    """Operators as built by the library's host builder (no GPU needed)."""
+    lib = library()
+    N = Ny - 2
+    G = (Nx // 2) * (Nz // 2)
+    out = {"ops": np.zeros((G, 4, N, N)), "mean_ops": np.zeros((2, N, N)), "lift": np.zeros(N),
+           "green": np.zeros(N), "D1": np.zeros((Ny, Ny)), "D1c": np.zeros((Ny, N)),
+           "ccw": np.zeros(Ny)}
+    g = Geometry(flow, Lx, Lz, Uw, 0.0)
+    rc = lib.dns_host_operators(ctypes.byref(g), Re, Nx, Ny, Nz, dt, h_index,
+                                *[_ptr(out[k]) for k in ("ops", "mean_ops", "lift", "green",
+                                                         "D1", "D1c", "ccw")])
+    if rc != DNS_OK:
+        raise DnsError(rc, lib.dns_last_error(None).decode())
+    return out
+
+
+class DnsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dns error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+class Ensemble:
+    """One ensemble of flows sharing grid, box, Re and dt (include/dns.h)."""
+
+    def __init__(self, flow, Re, Lx, Lz, Nx, Ny, Nz, ensemble, dt, Uw=1.0, flux=0.0):
+        self.lib = library()
+        self.flow, self.Re, self.Lx, self.Lz = flow, Re, Lx, Lz
+        self.Nx, self.Ny, self.Nz, self.E, self.dt = Nx, Ny, Nz, ensemble, dt
+        self.h = ctypes.c_void_p()
+        g = Geometry(flow, Lx, Lz, Uw, flux)
+        rc = self.lib.dns_create(ctypes.byref(g), Re, Nx, Ny, Nz, ensemble, dt, ctypes.byref(self.h))
+        if rc != DNS_OK:
+            raise DnsError(rc, self.lib.dns_last_error(None).decode())
+
+    # ---- helpers ---------------------------------------------------------------
+    def _check(self, rc):
+        if rc != DNS_OK:
+            raise DnsError(rc, self.lib.dns_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if self.h:
+            self.lib.dns_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def shape_spec(self):
+        return (self.Nx // 2, self.Nz - 1, self.Ny - 2)
+
+    # ---- C ABI calls -------------------------------------------------------------
+    def set_option(self, key, value):
+        return self._check(self.lib.dns_set_option(self.h, key, int(value)))
+
+    def set_precision(self, prec):
+        return self.set_option(OPT_PRECISION, prec)
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream (or its integer handle)."""
+        handle = getattr(stream, "cuda_stream", stream)
+        return self.set_option(OPT_STREAM, int(handle))
+
+    def set_state(self, v, eta, U, W, member0=0):
+        """Host numpy arrays in the state layout of include/dns.h."""
+        v = np.ascontiguousarray(v, dtype=np.complex128)
+        eta = np.ascontiguousarray(eta, dtype=np.complex128)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        count = v.shape[0]
+        if v.shape[1:] != self.shape_spec or eta.shape != v.shape or U.shape != (count, self.Ny) \
+                or W.shape != U.shape:
+            raise ValueError("state arrays do not match the grid")
+        sv = StateView(v.ctypes.data, eta.ctypes.data, U.ctypes.data, W.ctypes.data, 0)
+        return self._check(self.lib.dns_set_state(self.h, member0, count, ctypes.byref(sv)))
+
+    def set_state_device(self, v, eta, U, W, member0=0):
+        """torch device tensors (complex128 / float64, contiguous)."""
+        count = v.shape[0]
+        sv = StateView(v.data_ptr(), eta.data_ptr(), U.data_ptr(), W.data_ptr(), 1)
+        return self._check(self.lib.dns_set_state(self.h, member0, count, ctypes.byref(sv)))
+
+    def get_state(self, member0=0, count=None):
+        count = self.E - member0 if count is None else count
+        v = np.zeros((count,) + self.shape_spec, dtype=np.complex128)
+        eta = np.zeros_like(v)
+        U = np.zeros((count, self.Ny))
+        W = np.zeros_like(U)
+        sv = StateView(v.ctypes.data, eta.ctypes.data, U.ctypes.data, W.ctypes.data, 0)
+        self._check(self.lib.dns_get_state(self.h, member0, count, ctypes.byref(sv)))
+        return v, eta, U, W
+
+    def step(self, nsteps=1):
+        return self._check(self.lib.dns_step(self.h, int(nsteps)))
+
+    def sync(self):
+        return self._check(self.lib.dns_sync(self.h))
+
+    def stats_reset(self):
+        return self._check(self.lib.dns_stats_reset(self.h))
+
+    def stats(self, allow_nonfinite=False):
+        E, My = self.E, self.Ny
+        out = {k: np.zeros(E) for k in ("energy", "dissipation", "power", "flux", "gamma",
+                                         "div_max", "tau_lower", "tau_upper")}
+        out["failed"] = np.zeros(E, dtype=np.int32)
+        for k in ("U", "W", "urms", "vrms", "wrms", "uv"):
+            out[k] = np.zeros(My)
+        so = StatsOut()
+        for k, arr in out.items():
+            setattr(so, k, arr.ctypes.data_as(_IP if k == "failed" else _DP))
+        rc = self.lib.dns_stats(self.h, ctypes.byref(so))
+        if rc != DNS_OK and not (allow_nonfinite and rc == DNS_E_NONFINITE):
+            self._check(rc)
+        out["tau_w"], out["re_tau"] = so.tau_w, so.re_tau
+        out["samples"], out["steps"] = so.samples, so.steps
+        out["rc"] = rc
+        return out
+
+    def kernel_times(self, nreps=10):
+        """(plane_ms, mode_ms): average device time per launch, HIP events."""
+        p = ctypes.c_double()
+        m = ctypes.c_double()
+        self._check(self.lib.dns_kernel_times(self.h, int(nreps), ctypes.byref(p), ctypes.byref(m)))
+        return p.value, m.value
+
+    def debug_stage0(self):
+        E, My, L, NZ = self.E, self.Ny, self.Nx // 2, self.Nz - 1
+        vel = np.zeros((5, E, My, L, NZ), dtype=np.complex128)
+        nl = np.zeros((3, E, My, L, NZ), dtype=np.complex128)
+        means = np.zeros((2, E, My))
+        self._check(self.lib.dns_debug_stage0(
+            self.h, vel.view(np.float64).ctypes.data_as(_DP),
+            nl.view(np.float64).ctypes.data_as(_DP), _ptr(means)))
+        return vel, nl, means
