@@ -14,6 +14,7 @@
 // state at the start of the step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -43,9 +44,11 @@ struct dns_handle {
   double *hF = nullptr, *hG = nullptr, *hEU = nullptr, *hEW = nullptr;
   void *vel = nullptr, *nl = nullptr;
   double *means = nullptr, *psum = nullptr;
-  double *ops[2] = {nullptr, nullptr}, *mean_ops[2] = {nullptr, nullptr};
+  double *opsT[2] = {nullptr, nullptr}, *meanT[2] = {nullptr, nullptr};
+  double *D1intT = nullptr, *D1cT = nullptr, *D1T = nullptr;
+  int CRP = 16, SR = 0, TR = 0;
   double *lift[2] = {nullptr, nullptr}, *green[2] = {nullptr, nullptr};
-  double *D1 = nullptr, *D1c = nullptr, *ccw = nullptr;
+  double *D1 = nullptr, *ccw = nullptr;
   double* gamma = nullptr;
   int* failed = nullptr;
   unsigned long long* divmax = nullptr;
@@ -92,8 +95,9 @@ void free_all(dns_handle* h) {
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
   void* bufs[] = {h->v, h->eta, h->U, h->W, h->hF, h->hG, h->hEU, h->hEW, h->vel, h->nl,
-                  h->means, h->psum, h->ops[0], h->ops[1], h->mean_ops[0], h->mean_ops[1],
-                  h->lift[0], h->lift[1], h->green[0], h->green[1], h->D1, h->D1c, h->ccw,
+                  h->means, h->psum, h->opsT[0], h->opsT[1], h->meanT[0], h->meanT[1],
+                  h->D1intT, h->D1cT, h->D1T,
+                  h->lift[0], h->lift[1], h->green[0], h->green[1], h->D1, h->ccw,
                   h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging};
   for (void* p : bufs)
     if (p) hipFree(p);
@@ -125,13 +129,17 @@ ModeArgs mode_args(dns_handle* h, int stage) {
   a.vel = h->vel;
   a.nl = h->nl;
   a.means = h->means;
-  a.ops = h->ops[hi];
-  a.mean_ops = h->mean_ops[hi];
+  a.opsT = h->opsT[hi];
+  a.meanT = h->meanT[hi];
+  a.D1intT = h->D1intT;
+  a.D1cT = h->D1cT;
+  a.D1T = h->D1T;
   a.lift = h->lift[hi];
   a.green = h->green[hi];
-  a.D1 = h->D1;
-  a.D1c = h->D1c;
   a.ccw = h->ccw;
+  a.CRP = h->CRP;
+  a.SR = h->SR;
+  a.TR = h->TR;
   a.gamma = h->gamma;
   a.failed = h->failed;
   a.divmax = h->divmax;
@@ -300,6 +308,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   }
   h->ET = mode_member_tile(h->My, h->E);
   h->ntiles = (h->E + h->ET - 1) / h->ET;
+  mode_lds_geometry(h->My, h->ET, &h->CRP, &h->SR, &h->TR);
 
   HostOperators ho;
   if (build_operators(h->My, h->L, h->P, h->kxs, h->kzs, Re, dt, h->Ubot, h->Utop, &ho) != 0) {
@@ -333,14 +342,46 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   }
   ALLOC(h->means, 2 * MyE);
   ALLOC(h->psum, size_t(NPS) * MyE);
+  // operators in MFMA A-operand tile order
+  const int N = h->N, My = h->My;
+  std::vector<double> opsT[2], meanT[2];
+  {
+    std::vector<double> cat(size_t(N) * 2 * N);
+    auto concat = [&](const double* A, const double* B) {
+      for (int r = 0; r < N; ++r)
+        for (int k = 0; k < N; ++k) {
+          cat[size_t(r) * 2 * N + k] = A[size_t(r) * N + k];
+          cat[size_t(r) * 2 * N + N + k] = B[size_t(r) * N + k];
+        }
+      return tile_for_mfma(cat.data(), N, 2 * N, 2 * N);
+    };
+    const size_t nn = size_t(N) * N;
+    for (int hi = 0; hi < 2; ++hi) {
+      const size_t per = size_t((N + 15) / 16) * ((2 * N + 3) / 4) * 64;
+      opsT[hi].assign(size_t(h->G) * 2 * per, 0.0);
+      for (int g = 1; g < h->G; ++g) {
+        const double* base = ho.ops[hi].data() + size_t(g) * 4 * nn;
+        const std::vector<double> tv = concat(base, base + nn);
+        const std::vector<double> te = concat(base + 2 * nn, base + 3 * nn);
+        std::copy(tv.begin(), tv.end(), opsT[hi].begin() + size_t(g) * 2 * per);
+        std::copy(te.begin(), te.end(), opsT[hi].begin() + size_t(g) * 2 * per + per);
+      }
+      meanT[hi] = concat(ho.mean_ops[hi].data(), ho.mean_ops[hi].data() + nn);
+    }
+  }
+  const std::vector<double> D1intT = tile_for_mfma(ho.D1.data() + My, N, My, My);
+  const std::vector<double> D1cT = tile_for_mfma(ho.D1c.data(), My, N, N);
+  const std::vector<double> D1T = tile_for_mfma(ho.D1.data(), My, My, My);
   for (int hi = 0; hi < 2; ++hi) {
-    ALLOC(h->ops[hi], ho.ops[hi].size());
-    ALLOC(h->mean_ops[hi], ho.mean_ops[hi].size());
+    ALLOC(h->opsT[hi], opsT[hi].size());
+    ALLOC(h->meanT[hi], meanT[hi].size());
     ALLOC(h->lift[hi], ho.lift[hi].size());
     ALLOC(h->green[hi], ho.green[hi].size());
   }
+  ALLOC(h->D1intT, D1intT.size());
+  ALLOC(h->D1cT, D1cT.size());
+  ALLOC(h->D1T, D1T.size());
   ALLOC(h->D1, ho.D1.size());
-  ALLOC(h->D1c, ho.D1c.size());
   ALLOC(h->ccw, ho.ccw.size());
   ALLOC(h->gamma, size_t(h->E));
   ALLOC(h->failed, size_t(h->E));
@@ -357,13 +398,15 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   };
   bool ok = true;
   for (int hi = 0; hi < 2; ++hi) {
-    ok &= up(h->ops[hi], ho.ops[hi]) == hipSuccess;
-    ok &= up(h->mean_ops[hi], ho.mean_ops[hi]) == hipSuccess;
+    ok &= up(h->opsT[hi], opsT[hi]) == hipSuccess;
+    ok &= up(h->meanT[hi], meanT[hi]) == hipSuccess;
     ok &= up(h->lift[hi], ho.lift[hi]) == hipSuccess;
     ok &= up(h->green[hi], ho.green[hi]) == hipSuccess;
   }
+  ok &= up(h->D1intT, D1intT) == hipSuccess;
+  ok &= up(h->D1cT, D1cT) == hipSuccess;
+  ok &= up(h->D1T, D1T) == hipSuccess;
   ok &= up(h->D1, ho.D1) == hipSuccess;
-  ok &= up(h->D1c, ho.D1c) == hipSuccess;
   ok &= up(h->ccw, ho.ccw) == hipSuccess;
   // laminar state, zero history
   std::vector<double> Ul(MyE, 0.0);

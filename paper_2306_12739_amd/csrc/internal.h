@@ -48,13 +48,14 @@ struct ModeArgs {
   void* vel;          // complex VT [5][My][K][E] (written)
   const void* nl;     // complex VT [3][My][K][E] (read)
   const double* means;  // [2][My][E]
-  // operators
-  const double* ops;    // [G][4][N][N] for this h
-  const double* mean_ops;  // [2 (A_U, B_U)][N][N] for this h
+  // operators, pre-tiled for v_mfma_f64_16x16x4f64 (see tile_for_mfma)
+  const double* opsT;   // per group: [A_v | B_v] then [A_eta | B_eta], each N x 2N
+  const double* meanT;  // [A_U | B_U], N x 2N
+  const double* D1intT; // D1[1:My-1, :], N x My
+  const double* D1cT;   // D1c, My x N
+  const double* D1T;    // D1, My x My
   const double* lift;   // [N]
   const double* green;  // [N]
-  const double* D1;     // [My][My]
-  const double* D1c;    // [My][N]
   const double* ccw;    // [My] Clenshaw-Curtis weights
   // per-member outputs
   double* gamma;        // [E]
@@ -62,6 +63,7 @@ struct ModeArgs {
   unsigned long long* divmax;  // [E] (bit pattern of a non-negative double)
   // sizes and parameters
   int My, N, K, E, L, P, NZ, G, ET, ntiles;
+  int CRP, SR, TR;      // LDS geometry (mode_lds_geometry)
   double kxs, kzs, hdt, Ubot, Utop, Qtarget;
   int stage;      // 0, 1, 2: sub-step index; -1: velocities of the state only
   int poiseuille;
@@ -72,6 +74,12 @@ hipError_t launch_plane(int precision, int Nx, int Nz, const PlaneArgs& a, hipSt
 bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
 int mode_member_tile(int My, int E);
+void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR);
+
+// Row-major R x Kd matrix (row stride ldm) -> MFMA A-operand tiles: tile
+// (rt, kt), rt < ceil(R/16), kt < ceil(Kd/4), is 64 consecutive values with
+// lane l holding M[16 rt + l % 16][4 kt + l / 16] (zero outside the matrix).
+std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm);
 
 // layout transposes between the host state layout and the device layout
 hipError_t launch_state_to_device(const double* host_layout_dev, double* dev, int E0, int count,

@@ -14,8 +14,14 @@
 //    w = (i kx eta + i kz dv/dy)/k^2 with dv/dy from the clamped interpolant;
 //  * Eqs. (U00), (W00) with the Couette wall lift and, for the channel, a
 //    pressure gradient gamma that holds the bulk flux at its target.
-// Columns of the per-group matrices are (mode slot, member) pairs; rows are
-// Chebyshev nodes.  All arithmetic here is FP64.
+//
+// Every y contraction Y = M X is a real matrix (an operator or a Chebyshev
+// derivative) times real columns (re/im of every (mode, member) pair) and runs
+// on the FP64 matrix cores: v_mfma_f64_16x16x4f64, one 16x16 output tile per
+// wavefront, K in steps of 4.  Operators are stored pre-tiled in the MFMA A
+// lane order (tile (rt, kt) = 64 consecutive doubles, lane l holding
+// M[16 rt + l % 16][4 kt + l / 16]) so each A fragment is one coalesced 512 B
+// load; X lives in LDS as [k][column] so each B fragment is four 128 B rows.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -31,462 +37,424 @@ __device__ __forceinline__ int xcd_logical_m(int b, int nblk) {
 }
 
 constexpr int kNT = 256;
-constexpr int kMaxR = 16;  // rows per thread
+constexpr int kWaves = kNT / 64;
 
-struct dc {
-  double x, y;
-};
-__device__ __forceinline__ dc dadd(dc a, dc b) { return dc{a.x + b.x, a.y + b.y}; }
-__device__ __forceinline__ dc dsub(dc a, dc b) { return dc{a.x - b.x, a.y - b.y}; }
-__device__ __forceinline__ dc dscale(dc a, double s) { return dc{a.x * s, a.y * s}; }
-__device__ __forceinline__ dc dmuli(dc a, double s) { return dc{-a.y * s, a.x * s}; }  // i s a
-__device__ __forceinline__ dc dconj(dc a) { return dc{a.x, -a.y}; }
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <typename VT>
-__device__ __forceinline__ dc ld_vt(const VT* p) {
-  return dc{double(p[0]), double(p[1])};
-}
-template <typename VT>
-__device__ __forceinline__ void st_vt(VT* p, dc v) {
-  p[0] = VT(v.x);
-  p[1] = VT(v.y);
-}
-
-// acc[r] += sum_k M[(row_r + roff) * ldm + k + koff] * B[k][c], k in [k0, k1)
-// for the rows this thread owns (row_r = rg + r * nrg < nrows).
-__device__ __forceinline__ void contract(dc* acc, const double* __restrict__ M, int ldm, int roff,
-                                         int koff, const dc* B, int C, int c, int rg, int nrg,
-                                         int nrows, int row0, int k0, int k1) {
-#pragma unroll 1
-  for (int k = k0; k < k1; ++k) {
-    const dc x = B[k * C + c];
-#pragma unroll
-    for (int r = 0; r < kMaxR; ++r) {
-      const int row = row0 + rg + r * nrg;
-      if (row < nrows) {
-        const double m = M[size_t(row + roff) * ldm + k + koff];
-        acc[r].x = fma(m, x.x, acc[r].x);
-        acc[r].y = fma(m, x.y, acc[r].y);
-      }
+// Y = M X over every output tile of this workgroup; store(row, col, value) is
+// called once per element with row < 16 RT, col < 16 CT (the caller ignores
+// padding rows).  M: tiled operator (RT x KT tiles), X: LDS, row stride ldx.
+// D layout of v_mfma_f64_16x16x4f64: lane l, register r -> row l/16 + 4r, col l%16.
+template <class Store>
+__device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int RT, int KT,
+                                              const double* X, int ldx, int CT, Store store) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < RT * CT; t += kWaves) {
+    const int rt = t / CT, ct = t - rt * CT;
+    const double* a = Mt + size_t(rt) * KT * 64 + lane;
+    const double* b = X + lk * ldx + ct * 16 + lr;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    int kt = 0;
+    for (; kt + 4 <= KT; kt += 4) {
+      const double a0 = a[(kt + 0) * 64], a1 = a[(kt + 1) * 64];
+      const double a2 = a[(kt + 2) * 64], a3 = a[(kt + 3) * 64];
+      const double b0 = b[(4 * kt + 0) * ldx], b1 = b[(4 * kt + 4) * ldx];
+      const double b2 = b[(4 * kt + 8) * ldx], b3 = b[(4 * kt + 12) * ldx];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2, b2, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a3, b3, acc, 0, 0, 0);
     }
+    for (; kt < KT; ++kt)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kt * 64], b[4 * kt * ldx], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(rt * 16 + lk + 4 * r, ct * 16 + lr, acc[r]);
   }
+}
+
+template <typename VT>
+__device__ __forceinline__ void st_c(VT* p, double re, double im) {
+  p[0] = VT(re);
+  p[1] = VT(im);
 }
 
 }  // namespace
 
+// LDS (doubles, row stride CRP = real columns padded to 16):
+//   S  [SR][CRP]  v-solve stack [v0; -h dt F_c], later eta (rows 0..My-1)
+//   S2 [SR][CRP]  eta-solve stack [eta0; -h dt G_c], later dv/dy then u
+//   T  [TR][CRP]  Q = i kx N_u + i kz N_w, later v (rows 0..My-1)
+// SR >= max(4 KT(2N), My), TR >= 4 KT(My); padding rows are zero.
 template <typename VT>
 __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
-  extern __shared__ dc smem[];
+  extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int My = a.My, N = a.N, K = a.K, E = a.E, NZ = a.NZ, P = a.P, ET = a.ET;
-  const int C = 2 * ET;
-  const int nrg = kNT / C;
-  const int c = tid % C;
-  const int rg = tid / C;
-  const bool active_thread = rg < nrg;
-  dc* B0 = smem;
-  dc* B1 = smem + My * C;
-  dc* B2 = smem + 2 * My * C;
+  const int C = 2 * ET;           // complex columns: (slot, member)
+  const int CRP = a.CRP;          // real columns, padded to 16
+  const int CT = CRP / 16;
+  const int SR = a.SR, TR = a.TR;
+  double* S = smem;
+  double* S2 = S + size_t(SR) * CRP;
+  double* T = S2 + size_t(SR) * CRP;
   __shared__ double red[kNT];
+  __shared__ double gam_s[64];
 
   const int flat = xcd_logical_m(blockIdx.x, gridDim.x);
   const int g = flat / a.ntiles;
   const int tile = flat - g * a.ntiles;
   const int nx = g / P, az = g - nx * P;
-  const int slot = c / ET;
-  const int e = tile * ET + (c - slot * ET);
-  const bool colvalid = active_thread && e < E && (slot == 0 || az > 0);
-  const double kx = a.kxs * nx;
-  const double kz = (slot == 0 ? 1.0 : -1.0) * a.kzs * az;
-  const double k2 = kx * kx + kz * kz;
-  const int iz = slot == 0 ? az : NZ - az;
-  const int m = nx * NZ + iz;
   const bool mean_group = (g == 0);
   VT* vel = static_cast<VT*>(a.vel);
   const VT* nl = static_cast<const VT*>(a.nl);
   const int s = a.stage;
   const double hdt = a.hdt;
+  const size_t KE = size_t(K) * E;
 
-  auto velp = [&](int f, int i) -> VT* {
-    return vel + 2 * ((size_t(f) * My + i) * K * E + size_t(m) * E + e);
+  // column c -> (slot, member); real column 2c (re), 2c + 1 (im)
+  auto col_slot = [&](int c) { return c / ET; };
+  auto col_member = [&](int c) { return tile * ET + (c - (c / ET) * ET); };
+  auto col_valid = [&](int c) {
+    const int sl = c / ET;
+    return tile * ET + (c - sl * ET) < E && (sl == 0 || az > 0);
   };
-  auto nlp = [&](int f, int i) -> const VT* {
-    return nl + 2 * ((size_t(f) * My + i) * K * E + size_t(m) * E + e);
-  };
-  auto stp = [&](double* base, int i) -> double* {  // interior row i in [1, N]
-    return base + 2 * ((size_t(m) * N + (i - 1)) * E + e);
-  };
+  auto col_mode = [&](int c) { return nx * NZ + (c / ET == 0 ? az : NZ - az); };
+  auto col_kz = [&](int c) { return (c / ET == 0 ? 1.0 : -1.0) * a.kzs * az; };
+  const double kx = a.kxs * nx;
 
-  dc acc[kMaxR];
-  auto zero_acc = [&]() {
-#pragma unroll
-    for (int r = 0; r < kMaxR; ++r) acc[r] = dc{0.0, 0.0};
-  };
+  // zero all buffers (padding rows and columns must hold zeros)
+  for (int q = tid; q < (2 * SR + TR) * CRP; q += kNT) smem[q] = 0.0;
+  __syncthreads();
+
+  const int RTn = (N + 15) / 16, RTm = (My + 15) / 16;
+  const int KT2n = (2 * N + 3) / 4, KTm = (My + 3) / 4, KTn = (N + 3) / 4;
 
   if (!mean_group) {
     // ===================== fluctuation modes (k^2 > 0) =====================
     if (s >= 0) {
-      // right-hand-side ingredients on every node
-      for (int i = rg; i < My; i += nrg) {
-        if (!active_thread) break;
-        dc q{0.0, 0.0}, nv{0.0, 0.0}, gg{0.0, 0.0};
-        if (colvalid) {
-          const dc Nu = ld_vt(nlp(0, i)), Nv = ld_vt(nlp(1, i)), Nw = ld_vt(nlp(2, i));
-          q = dadd(dmuli(Nu, kx), dmuli(Nw, kz));
-          nv = dscale(Nv, -k2);
-          gg = dsub(dmuli(Nu, kz), dmuli(Nw, kx));
-        }
-        B0[i * C + c] = q;
-        B1[i * C + c] = nv;
-        B2[i * C + c] = gg;
-      }
-      __syncthreads();
-      // F = -k^2 N_v - D1 (i kx N_u + i kz N_w) on interior rows, in place in B1
-      zero_acc();
-      if (active_thread) contract(acc, a.D1, My, 0, 0, B0, C, c, rg, nrg, My - 1, 1, 0, My);
-      __syncthreads();
-      if (active_thread) {
-#pragma unroll
-        for (int r = 0; r < kMaxR; ++r) {
-          const int i = 1 + rg + r * nrg;
-          if (i < My - 1) B1[i * C + c] = dsub(B1[i * C + c], acc[r]);
+      for (int q = tid; q < My * C; q += kNT) {
+        const int i = q / C, c = q - i * C;
+        if (!col_valid(c)) continue;
+        const size_t off = 2 * ((size_t(0) * My + i) * KE + size_t(col_mode(c)) * E + col_member(c));
+        const size_t fs = 2 * size_t(My) * KE;
+        const double kz = col_kz(c), k2 = kx * kx + kz * kz;
+        const double nur = nl[off], nui = nl[off + 1];
+        const double nvr = nl[off + fs], nvi = nl[off + fs + 1];
+        const double nwr = nl[off + 2 * fs], nwi = nl[off + 2 * fs + 1];
+        // Q = i kx N_u + i kz N_w
+        T[i * CRP + 2 * c] = -(kx * nui + kz * nwi);
+        T[i * CRP + 2 * c + 1] = kx * nur + kz * nwr;
+        if (i >= 1 && i < My - 1) {
+          // -k^2 N_v into the lower half of S; G = i kz N_u - i kx N_w into S2
+          S[(N + i - 1) * CRP + 2 * c] = -k2 * nvr;
+          S[(N + i - 1) * CRP + 2 * c + 1] = -k2 * nvi;
+          S2[(N + i - 1) * CRP + 2 * c] = -(kz * nui - kx * nwi);
+          S2[(N + i - 1) * CRP + 2 * c + 1] = kz * nur - kx * nwr;
         }
       }
       __syncthreads();
-      // RK3 combination, history update, -h dt scaling; state v0 into B0
-      for (int i = 1 + rg; i < My - 1; i += nrg) {
-        if (!active_thread) break;
-        dc F = B1[i * C + c], G = B2[i * C + c];
-        dc v0{0.0, 0.0};
-        if (colvalid) {
-          double* hf = stp(a.hF, i);
-          double* hg = stp(a.hG, i);
-          if (s == 0) {
-            hf[0] = F.x; hf[1] = F.y;
-            hg[0] = G.x; hg[1] = G.y;
-          } else if (s == 1) {
-            const dc H{hf[0], hf[1]}, HG{hg[0], hg[1]};
-            const dc Fc = dsub(dscale(F, 2.0), H), Gc = dsub(dscale(G, 2.0), HG);
-            const dc Hn = dadd(H, dscale(F, 4.0)), HGn = dadd(HG, dscale(G, 4.0));
-            hf[0] = Hn.x; hf[1] = Hn.y;
-            hg[0] = HGn.x; hg[1] = HGn.y;
-            F = Fc;
-            G = Gc;
-          } else {
-            const dc H{hf[0], hf[1]}, HG{hg[0], hg[1]};
-            F = dscale(dadd(H, F), 1.0 / 6.0);
-            G = dscale(dadd(HG, G), 1.0 / 6.0);
-          }
-          const double* vp = stp(a.v, i);
-          v0 = dc{vp[0], vp[1]};
+      // F = -k^2 N_v - D1 Q on interior rows (D1int = D1[1:My-1, :])
+      mfma_contract(a.D1intT, RTn, KTm, T, CRP, CT, [&](int r, int cc, double v) {
+        if (r < N) S[(N + r) * CRP + cc] -= v;
+      });
+      __syncthreads();
+      // RK3 combination, history, -h dt scaling; v0 and eta0 into the stacks
+      for (int q = tid; q < N * C; q += kNT) {
+        const int ii = q / C, c = q - ii * C;
+        if (!col_valid(c)) continue;
+        const size_t so = 2 * ((size_t(col_mode(c)) * N + ii) * E + col_member(c));
+        double Fr = S[(N + ii) * CRP + 2 * c], Fi = S[(N + ii) * CRP + 2 * c + 1];
+        double Gr = S2[(N + ii) * CRP + 2 * c], Gi = S2[(N + ii) * CRP + 2 * c + 1];
+        double* hf = a.hF + so;
+        double* hg = a.hG + so;
+        if (s == 0) {
+          hf[0] = Fr; hf[1] = Fi;
+          hg[0] = Gr; hg[1] = Gi;
+        } else if (s == 1) {
+          const double Hr = hf[0], Hi = hf[1], HGr = hg[0], HGi = hg[1];
+          hf[0] = Hr + 4.0 * Fr; hf[1] = Hi + 4.0 * Fi;
+          hg[0] = HGr + 4.0 * Gr; hg[1] = HGi + 4.0 * Gi;
+          Fr = 2.0 * Fr - Hr; Fi = 2.0 * Fi - Hi;
+          Gr = 2.0 * Gr - HGr; Gi = 2.0 * Gi - HGi;
         } else {
-          F = dc{0.0, 0.0};
-          G = dc{0.0, 0.0};
+          Fr = (hf[0] + Fr) * (1.0 / 6.0); Fi = (hf[1] + Fi) * (1.0 / 6.0);
+          Gr = (hg[0] + Gr) * (1.0 / 6.0); Gi = (hg[1] + Gi) * (1.0 / 6.0);
         }
-        B1[i * C + c] = dscale(F, -hdt);
-        B2[i * C + c] = dscale(G, -hdt);
-        B0[i * C + c] = v0;
+        S[(N + ii) * CRP + 2 * c] = -hdt * Fr;
+        S[(N + ii) * CRP + 2 * c + 1] = -hdt * Fi;
+        S2[(N + ii) * CRP + 2 * c] = -hdt * Gr;
+        S2[(N + ii) * CRP + 2 * c + 1] = -hdt * Gi;
+        S[ii * CRP + 2 * c] = a.v[so];
+        S[ii * CRP + 2 * c + 1] = a.v[so + 1];
+        S2[ii * CRP + 2 * c] = a.eta[so];
+        S2[ii * CRP + 2 * c + 1] = a.eta[so + 1];
       }
       __syncthreads();
-      // v = A_v v0 + B_v (-h dt F_c)
-      const double* opg = a.ops + size_t(g) * 4 * N * N;
-      zero_acc();
-      if (active_thread) {
-        contract(acc, opg, N, -1, -1, B0, C, c, rg, nrg, My - 1, 1, 1, My - 1);
-        contract(acc, opg + size_t(N) * N, N, -1, -1, B1, C, c, rg, nrg, My - 1, 1, 1, My - 1);
-      }
+      const double* opg = a.opsT + size_t(g) * 2 * RTn * KT2n * 64;
+      // v = [A_v | B_v] [v0; -h dt F_c] -> T rows 1..N (Q no longer needed)
+      for (int q = tid; q < TR * CRP; q += kNT) T[q] = 0.0;
       __syncthreads();
-      if (active_thread) {
-#pragma unroll
-        for (int r = 0; r < kMaxR; ++r) {
-          const int i = 1 + rg + r * nrg;
-          if (i < My - 1) {
-            B0[i * C + c] = acc[r];
-            dc e0{0.0, 0.0};
-            if (colvalid) {
-              const double* ep = stp(a.eta, i);
-              e0 = dc{ep[0], ep[1]};
-            }
-            B1[i * C + c] = e0;
-          }
-        }
-      }
+      mfma_contract(opg, RTn, KT2n, S, CRP, CT, [&](int r, int cc, double v) {
+        if (r < N) T[(1 + r) * CRP + cc] = v;
+      });
       __syncthreads();
-      // eta = A_eta eta0 + B_eta (-h dt G_c)
-      zero_acc();
-      if (active_thread) {
-        contract(acc, opg + size_t(2) * N * N, N, -1, -1, B1, C, c, rg, nrg, My - 1, 1, 1, My - 1);
-        contract(acc, opg + size_t(3) * N * N, N, -1, -1, B2, C, c, rg, nrg, My - 1, 1, 1, My - 1);
-      }
+      // eta = [A_eta | B_eta] [eta0; -h dt G_c] -> S rows 1..N
+      for (int q = tid; q < SR * CRP; q += kNT) S[q] = 0.0;
       __syncthreads();
-      if (active_thread) {
-#pragma unroll
-        for (int r = 0; r < kMaxR; ++r) {
-          const int i = 1 + rg + r * nrg;
-          if (i < My - 1) B1[i * C + c] = acc[r];
-        }
-      }
+      mfma_contract(opg + size_t(RTn) * KT2n * 64, RTn, KT2n, S2, CRP, CT, [&](int r, int cc, double v) {
+        if (r < N) S[(1 + r) * CRP + cc] = v;
+      });
       __syncthreads();
       if (s == 2) {
         // Hermitian projection of the n_x = 0 column: (0, nz) and (0, -nz)
-        if (nx == 0 && az > 0 && active_thread && slot == 0) {
-          for (int i = 1 + rg; i < My - 1; i += nrg) {
-            const int cp = c + ET;
-            const dc va = B0[i * C + c], vb = B0[i * C + cp];
-            const dc ea = B1[i * C + c], eb = B1[i * C + cp];
-            const dc pv = dscale(dadd(va, dconj(vb)), 0.5);
-            const dc pe = dscale(dadd(ea, dconj(eb)), 0.5);
-            B0[i * C + c] = pv;
-            B0[i * C + cp] = dconj(pv);
-            B1[i * C + c] = pe;
-            B1[i * C + cp] = dconj(pe);
+        if (nx == 0 && az > 0) {
+          for (int q = tid; q < N * ET; q += kNT) {
+            const int ii = q / ET, c0 = q - ii * ET, c1 = c0 + ET;
+            const int i = ii + 1;
+            double* bufs[2] = {T, S};
+#pragma unroll
+            for (int bsel = 0; bsel < 2; ++bsel) {
+              double* B = bufs[bsel];
+              const double ar = B[i * CRP + 2 * c0], ai = B[i * CRP + 2 * c0 + 1];
+              const double br = B[i * CRP + 2 * c1], bi = B[i * CRP + 2 * c1 + 1];
+              const double pr = 0.5 * (ar + br), pi = 0.5 * (ai - bi);
+              B[i * CRP + 2 * c0] = pr;
+              B[i * CRP + 2 * c0 + 1] = pi;
+              B[i * CRP + 2 * c1] = pr;
+              B[i * CRP + 2 * c1 + 1] = -pi;
+            }
           }
+          __syncthreads();
         }
-        __syncthreads();
-        if (colvalid) {
-          for (int i = 1 + rg; i < My - 1; i += nrg) {
-            double* vp = stp(a.v, i);
-            double* ep = stp(a.eta, i);
-            const dc vv = B0[i * C + c], ee = B1[i * C + c];
-            vp[0] = vv.x; vp[1] = vv.y;
-            ep[0] = ee.x; ep[1] = ee.y;
-          }
+        for (int q = tid; q < N * C; q += kNT) {
+          const int ii = q / C, c = q - ii * C;
+          if (!col_valid(c)) continue;
+          const size_t so = 2 * ((size_t(col_mode(c)) * N + ii) * E + col_member(c));
+          a.v[so] = T[(ii + 1) * CRP + 2 * c];
+          a.v[so + 1] = T[(ii + 1) * CRP + 2 * c + 1];
+          a.eta[so] = S[(ii + 1) * CRP + 2 * c];
+          a.eta[so + 1] = S[(ii + 1) * CRP + 2 * c + 1];
         }
       }
     } else {
-      // velocities of the stored state only
-      for (int i = rg; i < My; i += nrg) {
-        if (!active_thread) break;
-        dc v0{0.0, 0.0}, e0{0.0, 0.0};
-        if (colvalid && i >= 1 && i < My - 1) {
-          const double* vp = stp(a.v, i);
-          const double* ep = stp(a.eta, i);
-          v0 = dc{vp[0], vp[1]};
-          e0 = dc{ep[0], ep[1]};
-        }
-        B0[i * C + c] = v0;
-        B1[i * C + c] = e0;
+      // velocities of the stored state: v -> T rows 1..N, eta -> S rows 1..N
+      for (int q = tid; q < N * C; q += kNT) {
+        const int ii = q / C, c = q - ii * C;
+        if (!col_valid(c)) continue;
+        const size_t so = 2 * ((size_t(col_mode(c)) * N + ii) * E + col_member(c));
+        T[(ii + 1) * CRP + 2 * c] = a.v[so];
+        T[(ii + 1) * CRP + 2 * c + 1] = a.v[so + 1];
+        S[(ii + 1) * CRP + 2 * c] = a.eta[so];
+        S[(ii + 1) * CRP + 2 * c + 1] = a.eta[so + 1];
       }
-      __syncthreads();
     }
-    // ---- velocity recovery: dv/dy = D1c v, u, w, then du/dy, dw/dy ----------
-    zero_acc();
-    if (active_thread) contract(acc, a.D1c, N, 0, -1, B0, C, c, rg, nrg, My, 0, 1, My - 1);
-    dc ur[kMaxR], wr[kMaxR];
+    __syncthreads();
+    // ---- velocity recovery: dv/dy = D1c v -> S2 rows 0..My-1 ---------------
+    for (int q = tid; q < SR * CRP; q += kNT) S2[q] = 0.0;
+    __syncthreads();
+    mfma_contract(a.D1cT, RTm, KTn, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < My) S2[r * CRP + cc] = v;
+    });
+    __syncthreads();
     double dmax = 0.0;
-    const double ik2 = k2 > 0.0 ? 1.0 / k2 : 0.0;
-    if (active_thread) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = rg + r * nrg;
-        if (i < My) {
-          const dc dv = acc[r];
-          const bool inner = i >= 1 && i < My - 1;
-          const dc et = inner ? B1[i * C + c] : dc{0.0, 0.0};
-          const dc vv = inner ? B0[i * C + c] : dc{0.0, 0.0};
-          const dc u = dscale(dsub(dmuli(dv, kx), dmuli(et, kz)), ik2);
-          const dc w = dscale(dadd(dmuli(et, kx), dmuli(dv, kz)), ik2);
-          ur[r] = u;
-          wr[r] = w;
-          if (colvalid) {
-            st_vt(velp(0, i), u);
-            st_vt(velp(1, i), vv);
-            st_vt(velp(2, i), w);
-            const dc dv_s = dadd(dadd(dmuli(u, kx), dv), dmuli(w, kz));
-            dmax = fmax(dmax, sqrt(dv_s.x * dv_s.x + dv_s.y * dv_s.y));
-          }
-        }
+    for (int q = tid; q < My * C; q += kNT) {
+      const int i = q / C, c = q - i * C;
+      const double kz = col_kz(c), k2 = kx * kx + kz * kz;
+      const double ik2 = k2 > 0.0 ? 1.0 / k2 : 0.0;
+      const double dr = S2[i * CRP + 2 * c], di = S2[i * CRP + 2 * c + 1];
+      const double er = S[i * CRP + 2 * c], ei = S[i * CRP + 2 * c + 1];
+      const double vr = T[i * CRP + 2 * c], vi = T[i * CRP + 2 * c + 1];
+      // u = (i kx dv - i kz eta) / k^2 ; w = (i kx eta + i kz dv) / k^2
+      const double ur = (-kx * di + kz * ei) * ik2, ui = (kx * dr - kz * er) * ik2;
+      const double wr = (-kx * ei - kz * di) * ik2, wi = (kx * er + kz * dr) * ik2;
+      S2[i * CRP + 2 * c] = ur;
+      S2[i * CRP + 2 * c + 1] = ui;
+      S[i * CRP + 2 * c] = wr;
+      S[i * CRP + 2 * c + 1] = wi;
+      if (col_valid(c)) {
+        const size_t off = 2 * ((size_t(i)) * KE + size_t(col_mode(c)) * E + col_member(c));
+        const size_t fs = 2 * size_t(My) * KE;
+        st_c(vel + off, ur, ui);
+        st_c(vel + off + fs, vr, vi);
+        st_c(vel + off + 2 * fs, wr, wi);
+        // divergence i kx u + dv/dy + i kz w
+        const double xr = -kx * ui + dr - kz * wi, xi = kx * ur + di + kz * wr;
+        dmax = fmax(dmax, sqrt(xr * xr + xi * xi));
       }
     }
     __syncthreads();
-    if (active_thread) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = rg + r * nrg;
-        if (i < My) {
-          B0[i * C + c] = ur[r];
-          B1[i * C + c] = wr[r];
+    // du/dy = D1 u, dw/dy = D1 w -> velocity fields 3 and 4
+    auto store_y = [&](int f, const double* Xsrc) {
+      mfma_contract(a.D1T, RTm, KTm, Xsrc, CRP, CT, [&](int r, int cc, double v) {
+        const int c = cc >> 1;
+        if (r < My && c < C && col_valid(c)) {
+          const size_t off = 2 * ((size_t(f) * My + r) * KE + size_t(col_mode(c)) * E + col_member(c));
+          vel[off + (cc & 1)] = VT(v);
         }
-      }
-    }
-    __syncthreads();
-    zero_acc();
-    if (active_thread) contract(acc, a.D1, My, 0, 0, B0, C, c, rg, nrg, My, 0, 0, My);
-    if (colvalid) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = rg + r * nrg;
-        if (i < My) st_vt(velp(3, i), acc[r]);
-      }
-    }
-    zero_acc();
-    if (active_thread) contract(acc, a.D1, My, 0, 0, B1, C, c, rg, nrg, My, 0, 0, My);
-    if (colvalid) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = rg + r * nrg;
-        if (i < My) st_vt(velp(4, i), acc[r]);
-      }
-    }
-    // per-member divergence maximum of this group (stage 2 and state-only calls)
+      });
+    };
+    store_y(3, S2);
+    store_y(4, S);
     if (s == 2 || s < 0) {
       red[tid] = dmax;
       __syncthreads();
-      if (tid < C && colvalid) {
+      // per member: max over the threads that saw its columns
+      if (tid < C && col_valid(tid)) {
         double mx = 0.0;
-        for (int q = 0; q < nrg; ++q) mx = fmax(mx, red[q * C + tid]);
-        atomicMax(&a.divmax[e], __double_as_longlong(mx));
+        for (int q = 0; q < kNT; ++q)
+          if ((q % C) == tid) mx = fmax(mx, red[q]);
+        atomicMax(&a.divmax[col_member(tid)], (unsigned long long)__double_as_longlong(mx));
       }
     }
     return;
   }
 
   // ========================= mean profiles (0, 0) ===========================
-  // Columns 0..ET-1 are members; U and W travel together as (re, im) of one
-  // complex column because they share the operators A_U, B_U (Eqs. (CN3), (CN4)).
-  const bool mcol = active_thread && slot == 0 && e < E;
+  // Real columns 2e (U or <uv> or E_U) and 2e + 1 (W or <wv> or E_W), e < ET;
+  // U and W share A_U, B_U (Eqs. (CN3), (CN4)).
+  const int NM = ET;  // members in this tile (slot 0 only)
   if (s >= 0) {
-    for (int i = rg; i < My; i += nrg) {
-      if (!active_thread) break;
-      dc uw{0.0, 0.0}, u0{0.0, 0.0};
-      if (mcol) {
-        uw = dc{a.means[(size_t(0) * My + i) * E + e], a.means[(size_t(1) * My + i) * E + e]};
-        u0 = dc{a.U[size_t(i) * E + e], a.W[size_t(i) * E + e]};
-      }
-      B0[i * C + c] = uw;
-      B2[i * C + c] = u0;
+    for (int q = tid; q < My * NM; q += kNT) {
+      const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+      if (e >= E) continue;
+      T[i * CRP + 2 * el] = a.means[(size_t(0) * My + i) * E + e];
+      T[i * CRP + 2 * el + 1] = a.means[(size_t(1) * My + i) * E + e];
     }
     __syncthreads();
-    // E_U + i E_W = -D1 (<uv> + i <wv>) on interior rows
-    zero_acc();
-    if (active_thread) contract(acc, a.D1, My, 0, 0, B0, C, c, rg, nrg, My - 1, 1, 0, My);
+    // E_U + E_W = -D1 (<uv>, <wv>) on interior rows -> S rows N..2N-1
+    mfma_contract(a.D1intT, RTn, KTm, T, CRP, CT, [&](int r, int cc, double v) {
+      if (r < N) S[(N + r) * CRP + cc] = -v;
+    });
     __syncthreads();
-    if (active_thread) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = 1 + rg + r * nrg;
-        if (i < My - 1) {
-          dc X = dscale(acc[r], -1.0);
-          if (mcol) {
-            double* hu = a.hEU + size_t(i - 1) * E + e;
-            double* hw = a.hEW + size_t(i - 1) * E + e;
-            if (s == 0) {
-              *hu = X.x;
-              *hw = X.y;
-            } else if (s == 1) {
-              const dc H{*hu, *hw};
-              *hu = H.x + 4.0 * X.x;
-              *hw = H.y + 4.0 * X.y;
-              X = dsub(dscale(X, 2.0), H);
-            } else {
-              const dc H{*hu, *hw};
-              X = dscale(dadd(H, X), 1.0 / 6.0);
-            }
-          } else {
-            X = dc{0.0, 0.0};
-          }
-          B1[i * C + c] = dscale(X, hdt);
+    for (int q = tid; q < N * NM; q += kNT) {
+      const int ii = q / NM, el = q - ii * NM, e = tile * ET + el;
+      if (e >= E) continue;
+      double xu = S[(N + ii) * CRP + 2 * el], xw = S[(N + ii) * CRP + 2 * el + 1];
+      double* hu = a.hEU + size_t(ii) * E + e;
+      double* hw = a.hEW + size_t(ii) * E + e;
+      if (s == 0) {
+        *hu = xu;
+        *hw = xw;
+      } else if (s == 1) {
+        const double Hu = *hu, Hw = *hw;
+        *hu = Hu + 4.0 * xu;
+        *hw = Hw + 4.0 * xw;
+        xu = 2.0 * xu - Hu;
+        xw = 2.0 * xw - Hw;
+      } else {
+        xu = (*hu + xu) * (1.0 / 6.0);
+        xw = (*hw + xw) * (1.0 / 6.0);
+      }
+      S[(N + ii) * CRP + 2 * el] = hdt * xu;
+      S[(N + ii) * CRP + 2 * el + 1] = hdt * xw;
+      S[ii * CRP + 2 * el] = a.U[size_t(ii + 1) * E + e];
+      S[ii * CRP + 2 * el + 1] = a.W[size_t(ii + 1) * E + e];
+    }
+    __syncthreads();
+    for (int q = tid; q < TR * CRP; q += kNT) T[q] = 0.0;
+    __syncthreads();
+    // (U_a, W) = [A_U | B_U] [(U0, W0); h dt (E_U,c, E_W,c)] -> T rows 1..N
+    mfma_contract(a.meanT, RTn, KT2n, S, CRP, CT, [&](int r, int cc, double v) {
+      if (r < N) T[(1 + r) * CRP + cc] = v;
+    });
+    __syncthreads();
+    // lift, bulk flux of the provisional U and gamma, one thread per member
+    if (tid < NM) {
+      const int el = tid, e = tile * ET + el;
+      double gam = 0.0;
+      if (a.poiseuille) {
+        double qa = a.ccw[0] * a.Ubot + a.ccw[My - 1] * a.Utop;
+        double wg = 0.0;
+        for (int i = 1; i < My - 1; ++i) {
+          qa += a.ccw[i] * (T[i * CRP + 2 * el] + a.lift[i - 1]);
+          wg += a.ccw[i] * a.green[i - 1];
         }
+        gam = (a.Qtarget - qa) / wg;
+      }
+      gam_s[el] = gam;
+      if (e < E) a.gamma[e] = gam;
+    }
+    __syncthreads();
+    for (int q = tid; q < My * NM; q += kNT) {
+      const int i = q / NM, el = q - i * NM;
+      if (i == 0) {
+        T[2 * el] = a.Ubot;
+        T[2 * el + 1] = 0.0;
+      } else if (i == My - 1) {
+        T[i * CRP + 2 * el] = a.Utop;
+        T[i * CRP + 2 * el + 1] = 0.0;
+      } else {
+        T[i * CRP + 2 * el] += a.lift[i - 1] + gam_s[el] * a.green[i - 1];
       }
     }
     __syncthreads();
-    // (U, W) = A_U (U0, W0) + B_U h dt (E_U,c, E_W,c) + (lift, 0)
-    zero_acc();
-    if (active_thread) {
-      contract(acc, a.mean_ops, N, -1, -1, B2, C, c, rg, nrg, My - 1, 1, 1, My - 1);
-      contract(acc, a.mean_ops + size_t(N) * N, N, -1, -1, B1, C, c, rg, nrg, My - 1, 1, 1, My - 1);
-    }
-    double qpart = 0.0;
-    if (active_thread) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = 1 + rg + r * nrg;
-        if (i < My - 1) {
-          acc[r].x += a.lift[i - 1];
-          qpart += a.ccw[i] * acc[r].x;
-        }
-      }
-    }
-    // bulk flux of the provisional U, reduced over rows in a fixed order
-    red[tid] = qpart;
-    __syncthreads();
-    double gam = 0.0;
-    if (a.poiseuille) {
-      double qa = a.ccw[0] * a.Ubot + a.ccw[My - 1] * a.Utop;
-      double wg = 0.0;
-      for (int q = 0; q < nrg; ++q) qa += red[q * C + c];
-      for (int i = 1; i < My - 1; ++i) wg += a.ccw[i] * a.green[i - 1];
-      gam = (a.Qtarget - qa) / wg;
-    }
-    __syncthreads();
-    if (active_thread) {
-#pragma unroll
-      for (int r = 0; r < kMaxR; ++r) {
-        const int i = 1 + rg + r * nrg;
-        if (i < My - 1) {
-          dc uw = acc[r];
-          uw.x += gam * a.green[i - 1];
-          B0[i * C + c] = uw;
-        }
-      }
-      if (rg == 0) {
-        B0[c] = dc{a.Ubot, 0.0};
-        B0[(My - 1) * C + c] = dc{a.Utop, 0.0};
-      }
-      if (mcol && rg == 0) a.gamma[e] = gam;
-    }
-    __syncthreads();
-    if (s == 2 && mcol) {
-      for (int i = rg; i < My; i += nrg) {
-        const dc uw = B0[i * C + c];
-        a.U[size_t(i) * E + e] = uw.x;
-        a.W[size_t(i) * E + e] = uw.y;
+    if (s == 2) {
+      for (int q = tid; q < My * NM; q += kNT) {
+        const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+        if (e >= E) continue;
+        a.U[size_t(i) * E + e] = T[i * CRP + 2 * el];
+        a.W[size_t(i) * E + e] = T[i * CRP + 2 * el + 1];
       }
     }
   } else {
-    for (int i = rg; i < My; i += nrg) {
-      if (!active_thread) break;
-      B0[i * C + c] = mcol ? dc{a.U[size_t(i) * E + e], a.W[size_t(i) * E + e]} : dc{0.0, 0.0};
+    for (int q = tid; q < My * NM; q += kNT) {
+      const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+      if (e >= E) continue;
+      T[i * CRP + 2 * el] = a.U[size_t(i) * E + e];
+      T[i * CRP + 2 * el + 1] = a.W[size_t(i) * E + e];
     }
     __syncthreads();
   }
   // velocity fields of the (0, 0) mode: u = U, v = 0, w = W, du/dy, dw/dy
-  zero_acc();
-  if (active_thread) contract(acc, a.D1, My, 0, 0, B0, C, c, rg, nrg, My, 0, 0, My);
-  if (mcol) {
-#pragma unroll
-    for (int r = 0; r < kMaxR; ++r) {
-      const int i = rg + r * nrg;
-      if (i < My) {
-        const dc uw = B0[i * C + c];
-        st_vt(velp(0, i), dc{uw.x, 0.0});
-        st_vt(velp(1, i), dc{0.0, 0.0});
-        st_vt(velp(2, i), dc{uw.y, 0.0});
-        st_vt(velp(3, i), dc{acc[r].x, 0.0});
-        st_vt(velp(4, i), dc{acc[r].y, 0.0});
-      }
-    }
+  for (int q = tid; q < My * NM; q += kNT) {
+    const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+    if (e >= E) continue;
+    const size_t off = 2 * (size_t(i) * KE + e);
+    const size_t fs = 2 * size_t(My) * KE;
+    st_c(vel + off, T[i * CRP + 2 * el], 0.0);
+    st_c(vel + off + fs, 0.0, 0.0);
+    st_c(vel + off + 2 * fs, T[i * CRP + 2 * el + 1], 0.0);
   }
+  mfma_contract(a.D1T, RTm, KTm, T, CRP, CT, [&](int r, int cc, double v) {
+    const int el = cc >> 1, e = tile * ET + el;
+    if (r < My && el < NM && e < E) {
+      const int f = 3 + (cc & 1);
+      const size_t off = 2 * ((size_t(f) * My + r) * KE + e);
+      st_c(vel + off, v, 0.0);
+    }
+  });
+}
+
+// LDS geometry of one workgroup; shared with the host launcher.
+void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR) {
+  const int N = My - 2;
+  *CRP = ((4 * ET + 15) / 16) * 16;
+  const int k2n = 4 * ((2 * N + 3) / 4);
+  const int km = 4 * ((My + 3) / 4);
+  int sr = k2n > My ? k2n : My;
+  // D1c reads T rows 1..4*KT(N); D1 reads rows 0..4*KT(My)-1
+  *SR = sr > km ? sr : km;
+  const int kn1 = 1 + 4 * ((N + 3) / 4);
+  *TR = km > kn1 ? km : kn1;
 }
 
 int mode_member_tile(int My, int E) {
-  // columns C = 2 * ET; keep three My x C complex-double buffers within ~80 KB
-  // and every thread's row count within kMaxR.
-  int et = 1;
-  while (et * 2 <= E && et * 2 <= 32) {
-    const int cand = et * 2;
-    const size_t lds = size_t(3) * My * 2 * cand * 16;
-    const int nrg = kNT / (2 * cand);
-    const int rows = (My + nrg - 1) / nrg;
-    if (lds > 80 * 1024 || rows > kMaxR) break;
-    et = cand;
+  // largest ET in {1, 2, 4, 8} (<= E) whose LDS stays within 128 KB
+  int best = 1;
+  for (int et = 1; et <= 8 && et <= E; et *= 2) {
+    int crp, sr, tr;
+    mode_lds_geometry(My, et, &crp, &sr, &tr);
+    const size_t lds = size_t(2 * sr + tr) * crp * sizeof(double);
+    if (lds <= 128 * 1024) best = et;
   }
-  return et;
+  return best;
 }
 
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   const int nblk = a.G * a.ntiles;
-  const size_t lds = size_t(3) * a.My * 2 * a.ET * sizeof(dc);
+  const size_t lds = size_t(2 * a.SR + a.TR) * a.CRP * sizeof(double);
   const void* fn = precision == 0 ? reinterpret_cast<const void*>(&mode_kernel<double>)
                                   : reinterpret_cast<const void*>(&mode_kernel<float>);
   hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));

@@ -216,6 +216,18 @@ ld fold_pair(const Mat& lhs, const Mat& rhs, int n, double* A, double* B) {
 
 }  // namespace
 
+std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm) {
+  const int RT = (R + 15) / 16, KT = (Kd + 3) / 4;
+  std::vector<double> out(size_t(RT) * KT * 64, 0.0);
+  for (int rt = 0; rt < RT; ++rt)
+    for (int kt = 0; kt < KT; ++kt)
+      for (int l = 0; l < 64; ++l) {
+        const int r = rt * 16 + l % 16, k = kt * 4 + l / 16;
+        if (r < R && k < Kd) out[(size_t(rt) * KT + kt) * 64 + l] = M[size_t(r) * ldm + k];
+      }
+  return out;
+}
+
 int build_operators(int My, int L, int P, double kxs, double kzs, double Re, double dt, double Ubot,
                     double Utop, HostOperators* out) {
   Cheb ch;
