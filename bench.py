@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -161,6 +163,13 @@ def main():
         print(f"warning: {int(s['failed'].sum())} members non-finite", file=sys.stderr)
 
     plane_ms, mode_ms = ens.kernel_times(args.kernel_reps)
+    if args.copy_calibration:
+        # reference kernel of known traffic: reads and writes exactly 256 MiB
+        with torch.cuda.stream(stream):
+            src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+        torch.cuda.synchronize()
     ens.close()
 
     ms_step = ms / args.steps

@@ -172,18 +172,32 @@ template <> struct Split<144> { static constexpr int A = 12, B = 12; };
 
 // Batched length-N transform, sign DIR, over NBATCH independent sequences,
 // executed by the whole workgroup (NT threads).  Stockham autosort:
-//   pass 1 (radix RA):  x[j + r*RB]         -> mid[b][j*RA + r]
-//   pass 2 (radix RB):  twiddle e^{DIR 2 pi i r k / N}, k = j < RA,
-//                       output element k + RA*t
+//   pass 1 (radix RA):  butterfly j < RB reads x[j + r*RB], r < RA, and keeps
+//                       its output r at mid[b][r][j]
+//   pass 2 (radix RB):  butterfly k < RA reads output k of every pass-1
+//                       butterfly, twiddles e^{DIR 2 pi i t k / N}, and hands
+//                       element k + RA*t of the transform to store()
+// The intermediate rows have an odd pitch (RB + 1) and the per-sequence pitch
+// is odd as well, so both passes touch distinct LDS banks across a wavefront.
 // load(b, n) returns input element n of sequence b; store(b, k, val) receives
-// output element k of sequence b exactly once.  mid holds NBATCH*N elements;
-// root[t] = e^{-2 pi i t / N}.  One barrier separates the passes; the caller
-// places barriers around the call when load/store touch shared memory.
+// output element k of sequence b exactly once.  mid holds NBATCH * MidPitch<N>
+// elements; root[t] = e^{-2 pi i t / N}.  One barrier separates the passes; the
+// caller places barriers around the call when load/store touch shared memory.
+template <int N>
+struct MidPitch {
+  static constexpr int row = Split<N>::B + 1;
+  static constexpr int raw = Split<N>::A * row;
+  static constexpr int value = (raw % 2) ? raw : raw + 1;
+};
+
 template <typename T, int N, int DIR, int NBATCH, int NT, class Load, class Store>
 __device__ __forceinline__ void fft2pass(cx<T>* mid, const cx<T>* root, Load load, Store store) {
   constexpr int RA = Split<N>::A;
   constexpr int RB = Split<N>::B;
+  constexpr int RP = MidPitch<N>::row;
+  constexpr int SP = MidPitch<N>::value;
   const int tid = threadIdx.x;
+#pragma unroll 1
   for (int it = tid; it < NBATCH * RB; it += NT) {
     const int b = it / RB, j = it - b * RB;
     cx<T> v[RA];
@@ -191,18 +205,19 @@ __device__ __forceinline__ void fft2pass(cx<T>* mid, const cx<T>* root, Load loa
     for (int r = 0; r < RA; ++r) v[r] = load(b, j + r * RB);
     SmallDft<T, RA, DIR>::run(v);
 #pragma unroll
-    for (int r = 0; r < RA; ++r) mid[b * N + j * RA + r] = v[r];
+    for (int r = 0; r < RA; ++r) mid[b * SP + r * RP + j] = v[r];
   }
   __syncthreads();
+#pragma unroll 1
   for (int it = tid; it < NBATCH * RA; it += NT) {
     const int b = it / RA, k = it - b * RA;
     cx<T> v[RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) v[r] = mid[b * N + k + r * RA];
+    for (int t = 0; t < RB; ++t) v[t] = mid[b * SP + k * RP + t];
 #pragma unroll
-    for (int r = 1; r < RB; ++r) {
-      const cx<T> w = root[r * k];  // r*k < N
-      v[r] = cmul(v[r], DIR > 0 ? cconj(w) : w);
+    for (int t = 1; t < RB; ++t) {
+      const cx<T> w = root[t * k];  // t*k < N
+      v[t] = cmul(v[t], DIR > 0 ? cconj(w) : w);
     }
     SmallDft<T, RB, DIR>::run(v);
 #pragma unroll

@@ -4,8 +4,10 @@
 // Device layouts (members innermost, "E" = ensemble size):
 //   state v, eta   : complex double [K][N][E]       K = Nx/2 * (Nz-1) modes
 //   state U, W     : double         [My][E]         walls included
-//   vel            : complex VT     [5][My][K][E]   u, v, w, du/dy, dw/dy
-//   nl             : complex VT     [3][My][K][E]   advection N_u, N_v, N_w
+//   vel            : complex VT     [5][My][E][K]   u, v, w, du/dy, dw/dy
+//   nl             : complex VT     [3][My][E][K]   advection N_u, N_v, N_w
+// (the two stage buffers are member-outer so that one plane workgroup's
+// spectral input is contiguous; see kernels_plane.hip)
 //   means          : double         [2][My][E]      <uv>, <wv>
 //   psum           : double         [NPS][My][E]    plane means for statistics
 //   hist F, G      : complex double [K][N][E]       RK3 forcing history
@@ -45,8 +47,8 @@ struct ModeArgs {
   double* hEU;   // [N][E]
   double* hEW;
   // pseudo-spectral stage buffers
-  void* vel;          // complex VT [5][My][K][E] (written)
-  const void* nl;     // complex VT [3][My][K][E] (read)
+  void* vel;          // complex VT [5][My][E][K] (written)
+  const void* nl;     // complex VT [3][My][E][K] (read)
   const double* means;  // [2][My][E]
   // operators, pre-tiled for v_mfma_f64_16x16x4f64 (see tile_for_mfma)
   const double* opsT;   // per group: [A_v | B_v] then [A_eta | B_eta], each N x 2N

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       for (int q = tid; q < My * C; q += kNT) {
         const int i = q / C, c = q - i * C;
         if (!col_valid(c)) continue;
-        const size_t off = 2 * ((size_t(0) * My + i) * KE + size_t(col_mode(c)) * E + col_member(c));
+        const size_t off = 2 * ((size_t(i) * E + col_member(c)) * K + col_mode(c));
         const size_t fs = 2 * size_t(My) * KE;
         const double kz = col_kz(c), k2 = kx * kx + kz * kz;
         const double nur = nl[off], nui = nl[off + 1];
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       S[i * CRP + 2 * c] = wr;
       S[i * CRP + 2 * c + 1] = wi;
       if (col_valid(c)) {
-        const size_t off = 2 * ((size_t(i)) * KE + size_t(col_mode(c)) * E + col_member(c));
+        const size_t off = 2 * ((size_t(i) * E + col_member(c)) * K + col_mode(c));
         const size_t fs = 2 * size_t(My) * KE;
         st_c(vel + off, ur, ui);
         st_c(vel + off + fs, vr, vi);
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       mfma_contract(a.D1T, RTm, KTm, Xsrc, CRP, CT, [&](int r, int cc, double v) {
         const int c = cc >> 1;
         if (r < My && c < C && col_valid(c)) {
-          const size_t off = 2 * ((size_t(f) * My + r) * KE + size_t(col_mode(c)) * E + col_member(c));
+          const size_t off = 2 * (((size_t(f) * My + r) * E + col_member(c)) * K + col_mode(c));
           vel[off + (cc & 1)] = VT(v);
         }
       });
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   for (int q = tid; q < My * NM; q += kNT) {
     const int i = q / NM, el = q - i * NM, e = tile * ET + el;
     if (e >= E) continue;
-    const size_t off = 2 * (size_t(i) * KE + e);
+    const size_t off = 2 * ((size_t(i) * E + e) * K);
     const size_t fs = 2 * size_t(My) * KE;
     st_c(vel + off, T[i * CRP + 2 * el], 0.0);
     st_c(vel + off + fs, 0.0, 0.0);
@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     const int el = cc >> 1, e = tile * ET + el;
     if (r < My && el < NM && e < E) {
       const int f = 3 + (cc & 1);
-      const size_t off = 2 * ((size_t(f) * My + r) * KE + e);
+      const size_t off = 2 * (((size_t(f) * My + r) * E + e) * K);
       st_c(vel + off, v, 0.0);
     }
   });

@@ -64,14 +64,18 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-constexpr int kNT = 256;
+constexpr int kNT = 512;
 
 template <typename T, int L, int P, int PP>
 struct PlaneCfg {
   static constexpr int MX = 3 * L, MZ = 3 * P, NZ = 2 * P - 1;
   static constexpr int R = MZ / PP, PH = PP / 2;
-  static constexpr int ZB = 3 * L * PP;                       // complex elements
-  static constexpr int MIDZ = 3 * L * PP, MIDX = 3 * PH * MX;
+  // LDS pitches (odd, to spread consecutive rows over the banks)
+  static constexpr int ZP = L + 1;                             // z-transform output rows [q][nx]
+  static constexpr int FP = 2 * L + 1;                         // forward x rows [pair][kx]
+  static constexpr int ZB0 = 3 * PP * ZP, ZB1 = 3 * PH * FP, ZB2 = 3 * L * PP;
+  static constexpr int ZB = ZB0 > ZB1 ? (ZB0 > ZB2 ? ZB0 : ZB2) : (ZB1 > ZB2 ? ZB1 : ZB2);
+  static constexpr int MIDZ = 3 * L * MidPitch<PP>::value, MIDX = 3 * PH * MidPitch<MX>::value;
   static constexpr int MID = MIDZ > MIDX ? MIDZ : MIDX;
   static constexpr int NPT = PP * MX;                          // physical points per chunk
   static constexpr int NACC = (3 * L * NZ + kNT - 1) / kNT;
@@ -119,7 +123,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
 
   // spectral input element (field f, nx, iz) of this (j, e), as complex T
   auto vel_at = [&](int f, int nx, int iz) -> C {
-    const size_t off = ((size_t(f) * My + j) * K + size_t(nx) * NZ + iz) * E + e;
+    const size_t off = ((size_t(f) * My + j) * E + e) * K + size_t(nx) * NZ + iz;
     return ldc<T>(vel + 2 * off);
   };
 
@@ -130,12 +134,19 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   double s_uv = 0.0, s_wv = 0.0, s_uu = 0.0, s_vv = 0.0, s_ww = 0.0, s_grad = 0.0;
 
   for (int r = 0; r < R; ++r) {
-    // ---- z inverse of NF spectral fields into zb[fi][nx][q] ----------------
+    // ---- z inverse of NF spectral fields into zb[fi][q][nx] ----------------
+    // The fold y[n'] = sum_a x[n' + PP a] e^{2 pi i (n' + PP a) r / Mz} is done
+    // first, by the whole workgroup with consecutive threads on consecutive kz
+    // (contiguous in the member-outer stage buffer), into zb[fi][n'][nx]; the
+    // transform then reads LDS only and writes its output back to zb.
     auto zinv = [&](auto nf_tag, int fbase, bool dz) {
       constexpr int NF = decltype(nf_tag)::value;
-      auto load = [&](int b, int np) -> C {
-        const int fi = b / L, nx = b - fi * L;
-        C s{T(0), T(0)};
+#pragma unroll 1
+      for (int it = tid; it < NF * L * PP; it += kNT) {
+        const int np = it % PP;
+        const int rest = it / PP;
+        const int nx = rest % L, fi = rest / L;
+        C acc_f{T(0), T(0)};
 #pragma unroll
         for (int fold = 0; fold < R; ++fold) {
           const int n = np + PP * fold;
@@ -145,12 +156,19 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
           else continue;
           C x = vel_at(fbase + fi, nx, nz >= 0 ? nz : nz + NZ);
           if (dz) x = cmuli<1>(cscale(x, kzs * T(nz)));
-          const int t = (n * r) % MZ;
-          s = cadd(s, cmul(x, cconj(rootZ[t])));
+          acc_f = cadd(acc_f, cmul(x, cconj(rootZ[(n * r) % MZ])));
         }
-        return s;
+        zb[(fi * PP + np) * Cfg::ZP + nx] = acc_f;
+      }
+      __syncthreads();
+      auto load = [&](int b, int np) -> C {
+        const int fi = b / L, nx = b - fi * L;
+        return zb[(fi * PP + np) * Cfg::ZP + nx];
       };
-      auto store = [&](int b, int q, C v) { zb[b * PP + q] = v; };
+      auto store = [&](int b, int q, C v) {
+        const int fi = b / L, nx = b - fi * L;
+        zb[(fi * PP + q) * Cfg::ZP + nx] = v;
+      };
       fft2pass<T, PP, +1, NF * L, kNT>(mid, rootP, load, store);
     };
     // ---- x inverse of NF fields held in zb, rows paired (q, q + PH) -------
@@ -158,15 +176,15 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       constexpr int NF = decltype(nf_tag)::value;
       auto load = [&](int b, int n) -> C {
         const int fi = b / PH, qp = b - fi * PH;
-        const C* col = zb + fi * L * PP;
+        const C* col = zb + fi * PP * Cfg::ZP;
         auto cval = [&](int nx, int q) -> C {
-          C c = col[nx * PP + q];
+          C c = col[q * Cfg::ZP + nx];
           if (dx) c = cmuli<1>(cscale(c, kxs * T(nx)));
           return c;
         };
         if (n == 0) {
           if (dx) return C{T(0), T(0)};
-          return C{col[qp].x, col[PH + qp].x};
+          return C{col[qp * Cfg::ZP].x, col[(PH + qp) * Cfg::ZP].x};
         }
         if (n < L) {
           const C c0 = cval(n, qp), c1 = cval(n, qp + PH);
@@ -248,8 +266,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
         return C{phys[PNU + f][qp * MX + n], phys[PNU + f][(qp + PH) * MX + n]};
       };
       auto store = [&](int b, int k, C v) {
-        if (k < L) zb[b * 2 * L + k] = v;
-        else if (k > MX - L) zb[b * 2 * L + k - MX + 2 * L] = v;
+        if (k < L) zb[b * Cfg::FP + k] = v;
+        else if (k > MX - L) zb[b * Cfg::FP + k - MX + 2 * L] = v;
       };
       fft2pass<T, MX, -1, 3 * PH, kNT>(mid, rootX, load, store);
     }
@@ -259,7 +277,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       auto load = [&](int b, int q) -> C {
         const int f = b / L, nx = b - f * L;
         const int qp = q < PH ? q : q - PH;
-        const C* row = zb + (f * PH + qp) * 2 * L;
+        const C* row = zb + (f * PH + qp) * Cfg::FP;
         const C zk = row[nx];
         const C zm = cconj(row[nx == 0 ? 0 : 2 * L - nx]);
         if (q < PH) return C{T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y + zm.y)};
@@ -296,7 +314,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     if (idx < 3 * L * NZ) {
       const int f = idx / (L * NZ);
       const int m = idx - f * L * NZ;
-      const size_t off = ((size_t(f) * My + j) * K + m) * E + e;
+      const size_t off = ((size_t(f) * My + j) * E + e) * K + m;
       stc<T>(nl + 2 * off, cscale(acc[k], inv));
     }
   }
