@@ -193,16 +193,23 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       }
       __syncthreads();
       const double* opg = a.opsT + size_t(g) * 2 * RTn * KT2n * 64;
-      // v = [A_v | B_v] [v0; -h dt F_c] -> T rows 1..N (Q no longer needed)
-      for (int q = tid; q < TR * CRP; q += kNT) T[q] = 0.0;
-      __syncthreads();
+      // v = [A_v | B_v] [v0; -h dt F_c] -> T rows 1..N (Q no longer needed;
+      // its wall rows 0 and My-1 must read as v = 0 later)
+      for (int q = tid; q < CRP; q += kNT) {
+        T[q] = 0.0;
+        T[(My - 1) * CRP + q] = 0.0;
+      }
       mfma_contract(opg, RTn, KT2n, S, CRP, CT, [&](int r, int cc, double v) {
         if (r < N) T[(1 + r) * CRP + cc] = v;
       });
       __syncthreads();
-      // eta = [A_eta | B_eta] [eta0; -h dt G_c] -> S rows 1..N
-      for (int q = tid; q < SR * CRP; q += kNT) S[q] = 0.0;
-      __syncthreads();
+      // eta = [A_eta | B_eta] [eta0; -h dt G_c] -> S rows 1..N; S rows 0 and
+      // My-1 become the eta wall values (zero).  Rows beyond My keep finite
+      // stack data that only meets the zero padding columns of D1.
+      for (int q = tid; q < CRP; q += kNT) {
+        S[q] = 0.0;
+        S[(My - 1) * CRP + q] = 0.0;
+      }
       mfma_contract(opg + size_t(RTn) * KT2n * 64, RTn, KT2n, S2, CRP, CT, [&](int r, int cc, double v) {
         if (r < N) S[(1 + r) * CRP + cc] = v;
       });
@@ -252,8 +259,6 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     }
     __syncthreads();
     // ---- velocity recovery: dv/dy = D1c v -> S2 rows 0..My-1 ---------------
-    for (int q = tid; q < SR * CRP; q += kNT) S2[q] = 0.0;
-    __syncthreads();
     mfma_contract(a.D1cT, RTm, KTn, T + CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < My) S2[r * CRP + cc] = v;
     });
@@ -353,8 +358,6 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       S[ii * CRP + 2 * el + 1] = a.W[size_t(ii + 1) * E + e];
     }
     __syncthreads();
-    for (int q = tid; q < TR * CRP; q += kNT) T[q] = 0.0;
-    __syncthreads();
     // (U_a, W) = [A_U | B_U] [(U0, W0); h dt (E_U,c, E_W,c)] -> T rows 1..N
     mfma_contract(a.meanT, RTn, KT2n, S, CRP, CT, [&](int r, int cc, double v) {
       if (r < N) T[(1 + r) * CRP + cc] = v;
@@ -441,13 +444,13 @@ void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR) {
 }
 
 int mode_member_tile(int My, int E) {
-  // largest ET in {1, 2, 4, 8} (<= E) whose LDS stays within 128 KB
+  // largest ET in {1, 2, 4, 8} (<= E) whose LDS allows two workgroups per CU
   int best = 1;
   for (int et = 1; et <= 8 && et <= E; et *= 2) {
     int crp, sr, tr;
     mode_lds_geometry(My, et, &crp, &sr, &tr);
     const size_t lds = size_t(2 * sr + tr) * crp * sizeof(double);
-    if (lds <= 128 * 1024) best = et;
+    if (lds <= 78 * 1024) best = et;
   }
   return best;
 }
