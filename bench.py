@@ -67,11 +67,17 @@ def kernel_model(w, E, precision):
     zfwd = 3 * L * 5 * Mz * np.log2(Mz)
     plane_flops = (zinv + xinv + prod + xfwd + zfwd) * My * E
     # per-(kx,kz) kernel (second sub-step): N spectra in, velocity spectra out,
-    # state and history in FP64, operators A_v, B_v, A_eta, B_eta once per group
+    # state in and history in/out in FP64, and the y-parity halves of
+    # [A_v | B_v] and [A_eta | B_eta] once per group
+    He, Ho = (N + 1) // 2, N // 2
+    Fe, Fo = He + 1, Ho + 1
+    op_words = 2 * (He * 2 * He + Ho * 2 * Ho)
     mode_bytes = (3 + 5) * My * K * E * cplx + 2 * K * N * E * 16 + 2 * 2 * K * N * E * 16 \
-        + G * 4 * N * N * 8
+        + G * op_words * 8
     cols = 2 * K * E  # real columns over all modes
-    mode_flops = cols * (2 * 2 * N * N * 2 + My * My * 2 + My * N * 2 + 2 * My * My * 2)
+    macs = 2 * (2 * He * He + 2 * Ho * Ho) + (Ho * Fe + He * Fo) + (Fo * He + Fe * Ho) \
+        + 2 * 2 * Fe * Fo
+    mode_flops = cols * 2 * macs
     return {"plane": (plane_bytes, plane_flops), "mode": (mode_bytes, mode_flops)}
 
 

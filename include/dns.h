@@ -70,6 +70,39 @@ typedef struct {
 int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ensemble, double dt,
                dns_handle** out);
 
+/* Several ensembles advanced together (Sec. 3.2 batches members of one
+ * configuration; here independent configurations -- different Re, grid, box,
+ * dt or flow -- share one dns_step).  Each group is a full ensemble as made by
+ * dns_create, with its own operators and buffers; its kernels run on a stream
+ * of its own, forked from and joined back into the grouped handle's stream
+ * (one hipGraph with one branch per group when DNS_OPT_GRAPH is on), so small
+ * groups overlap on the device.  Members are numbered group-major: group g
+ * holds members [sum of earlier groups' members, + members).
+ *   groups  : ngroups descriptions, 1 <= ngroups <= DNS_MAX_GROUPS; read only
+ *             during the call.
+ * On a grouped handle: dns_set_state / dns_get_state take member ranges inside
+ * one group (in that group's state layout); dns_stats fills the per-member
+ * arrays (group-major) and requires every profile pointer to be NULL (profiles
+ * differ per group: read them from the group's handle); DNS_OPT_PRECISION and
+ * DNS_OPT_STATS apply to every group; dns_debug_stage0 and dns_kernel_times
+ * need a group's handle.  Errors as dns_create, the message naming the group. */
+#define DNS_MAX_GROUPS 16
+typedef struct {
+  dns_geometry g;
+  double Re;
+  int Nx, Ny, Nz;
+  int members;
+  double dt;
+} dns_group;
+int dns_create_grouped(const dns_group* groups, int ngroups, dns_handle** out);
+
+/* Handle of group `group` of a grouped handle, for the per-group calls
+ * (statistics with profiles, state I/O in local member numbers, kernel times).
+ * The grouped handle owns it: dns_destroy on it does nothing, and it is freed
+ * with the grouped handle.  Calls on it wait for the grouped handle's queued
+ * work first.  Errors: DNS_E_INVALID (not grouped, group out of range). */
+int dns_group_handle(dns_handle* h, int group, dns_handle** out);
+
 /* Options (dns_set_option keys) */
 #define DNS_OPT_PRECISION 1   /* value: DNS_PREC_*                                */
 #define DNS_OPT_STREAM 2      /* value: hipStream_t cast to integer (0 = default) */

@@ -45,10 +45,12 @@ struct dns_handle {
   void *vel = nullptr, *nl = nullptr;
   double *means = nullptr, *psum = nullptr;
   double *opsT[2] = {nullptr, nullptr}, *meanT[2] = {nullptr, nullptr};
-  double *D1intT = nullptr, *D1cT = nullptr, *D1T = nullptr;
+  size_t op_group_stride = 0;
+  double *D1intT_e = nullptr, *D1intT_o = nullptr, *D1cT_e = nullptr, *D1cT_o = nullptr;
+  double *D1T_e = nullptr, *D1T_o = nullptr;
   int CRP = 16, SR = 0, TR = 0;
-  double *lift[2] = {nullptr, nullptr}, *green[2] = {nullptr, nullptr};
-  double *D1 = nullptr, *ccw = nullptr;
+  double *lift_h[2] = {nullptr, nullptr}, *green_h[2] = {nullptr, nullptr};
+  double *ccw_h = nullptr, *D1 = nullptr, *ccw = nullptr;
   double* gamma = nullptr;
   int* failed = nullptr;
   unsigned long long* divmax = nullptr;
@@ -64,6 +66,15 @@ struct dns_handle {
   bool graph_valid = false;
   double max_cond = 0.0;
   std::string err;
+  // grouped handle: ensembles of different grid, Re, box or dt advanced by one
+  // dns_step (members numbered group-major); each group runs on its own stream,
+  // forked from and joined back into this handle's stream
+  std::vector<dns_handle*> sub;
+  std::vector<int> sub_base;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
+  dns_handle* parent = nullptr;
+  bool grouped() const { return !sub.empty(); }
 };
 
 namespace {
@@ -91,13 +102,28 @@ hipError_t dalloc(T** p, size_t count) {
 
 size_t vt_size(int precision) { return precision == DNS_PREC_FP64 ? sizeof(double) : sizeof(float); }
 
+void destroy_one(dns_handle* h);
+
 void free_all(dns_handle* h) {
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  for (dns_handle* s : h->sub) {
+    s->parent = nullptr;
+    destroy_one(s);
+  }
+  h->sub.clear();
+  for (hipEvent_t e : h->join)
+    if (e) hipEventDestroy(e);
+  h->join.clear();
+  if (h->fork) hipEventDestroy(h->fork);
+  h->fork = nullptr;
   void* bufs[] = {h->v, h->eta, h->U, h->W, h->hF, h->hG, h->hEU, h->hEW, h->vel, h->nl,
                   h->means, h->psum, h->opsT[0], h->opsT[1], h->meanT[0], h->meanT[1],
-                  h->D1intT, h->D1cT, h->D1T,
-                  h->lift[0], h->lift[1], h->green[0], h->green[1], h->D1, h->ccw,
+                  h->D1intT_e, h->D1intT_o, h->D1cT_e, h->D1cT_o, h->D1T_e, h->D1T_o,
+                  h->lift_h[0], h->lift_h[1], h->green_h[0], h->green_h[1], h->ccw_h,
+                  h->D1, h->ccw,
                   h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging};
   for (void* p : bufs)
     if (p) hipFree(p);
@@ -130,13 +156,17 @@ ModeArgs mode_args(dns_handle* h, int stage) {
   a.nl = h->nl;
   a.means = h->means;
   a.opsT = h->opsT[hi];
+  a.op_group_stride = h->op_group_stride;
   a.meanT = h->meanT[hi];
-  a.D1intT = h->D1intT;
-  a.D1cT = h->D1cT;
-  a.D1T = h->D1T;
-  a.lift = h->lift[hi];
-  a.green = h->green[hi];
-  a.ccw = h->ccw;
+  a.D1intT_e = h->D1intT_e;
+  a.D1intT_o = h->D1intT_o;
+  a.D1cT_e = h->D1cT_e;
+  a.D1cT_o = h->D1cT_o;
+  a.D1T_e = h->D1T_e;
+  a.D1T_o = h->D1T_o;
+  a.lift_h = h->lift_h[hi];
+  a.green_h = h->green_h[hi];
+  a.ccw_h = h->ccw_h;
   a.CRP = h->CRP;
   a.SR = h->SR;
   a.TR = h->TR;
@@ -222,12 +252,30 @@ void invalidate_graph(dns_handle* h) {
   h->gexec = nullptr;
   h->graph = nullptr;
   h->graph_valid = false;
+  if (h->parent) invalidate_graph(h->parent);  // a group's change stales the joint graph
 }
+
+// One step of every group: fork from h->stream, each group's kernels on its own
+// stream (independent, so the device overlaps them), join back.
+int enqueue_grouped(dns_handle* h) {
+  HIP_OR_FAIL(h, hipEventRecord(h->fork, h->stream));
+  for (size_t g = 0; g < h->sub.size(); ++g) {
+    dns_handle* s = h->sub[g];
+    HIP_OR_FAIL(h, hipStreamWaitEvent(s->stream, h->fork, 0));
+    const int rc = enqueue_step(s);
+    if (rc) return fail(h, rc, "group " + std::to_string(g) + ": " + s->err);
+    HIP_OR_FAIL(h, hipEventRecord(h->join[g], s->stream));
+    HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->join[g], 0));
+  }
+  return DNS_OK;
+}
+
+int enqueue_any(dns_handle* h) { return h->grouped() ? enqueue_grouped(h) : enqueue_step(h); }
 
 int build_graph(dns_handle* h) {
   invalidate_graph(h);
   HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_step(h);
+  int rc = enqueue_any(h);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (rc != DNS_OK) {
@@ -251,6 +299,48 @@ int any_failed(dns_handle* h, std::vector<int>* flags) {
   for (int x : f) any |= x;
   if (flags) *flags = f;
   return any;
+}
+
+void destroy_one(dns_handle* h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+}
+
+// Group g holding member m of a grouped handle, or -1.
+int group_of(const dns_handle* h, int m) {
+  for (size_t g = 0; g < h->sub.size(); ++g)
+    if (m >= h->sub_base[g] && m < h->sub_base[g] + h->sub[g]->E) return int(g);
+  return -1;
+}
+
+// Route a member range of a grouped handle to its group; the range must lie in one group.
+int route(dns_handle* h, int member0, int count, dns_handle** s, int* local0) {
+  const int g = member0 >= 0 && count >= 1 ? group_of(h, member0) : -1;
+  if (g < 0 || member0 + count > h->sub_base[g] + h->sub[g]->E)
+    return fail(h, DNS_E_INVALID, "member range must lie inside one group");
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  *s = h->sub[g];
+  *local0 = member0 - h->sub_base[g];
+  return DNS_OK;
+}
+
+// Calls on a group's handle are ordered after the work its grouped handle has queued.
+int after_parent(dns_handle* h) {
+  if (h->parent) HIP_OR_FAIL(h, hipStreamSynchronize(h->parent->stream));
+  return DNS_OK;
+}
+
+#define ORDER_AFTER_PARENT(h)       \
+  do {                              \
+    const int rc_ = after_parent(h); \
+    if (rc_) return rc_;            \
+  } while (0)
+
+int forward(dns_handle* h, dns_handle* s, int rc) {
+  if (rc != DNS_OK) return fail(h, rc, s->err);
+  return DNS_OK;
 }
 
 int check_dims(int Nx, int Ny, int Nz, int E) {
@@ -342,45 +432,81 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   }
   ALLOC(h->means, 2 * MyE);
   ALLOC(h->psum, size_t(NPS) * MyE);
-  // operators in MFMA A-operand tile order
+  // Operators split by y parity (each CN operator commutes with the reflection
+  // y -> -y, each D1 anticommutes with it), in MFMA A-operand tile order.
   const int N = h->N, My = h->My;
-  std::vector<double> opsT[2], meanT[2];
-  {
-    std::vector<double> cat(size_t(N) * 2 * N);
-    auto concat = [&](const double* A, const double* B) {
-      for (int r = 0; r < N; ++r)
-        for (int k = 0; k < N; ++k) {
-          cat[size_t(r) * 2 * N + k] = A[size_t(r) * N + k];
-          cat[size_t(r) * 2 * N + N + k] = B[size_t(r) * N + k];
-        }
-      return tile_for_mfma(cat.data(), N, 2 * N, 2 * N);
-    };
-    const size_t nn = size_t(N) * N;
-    for (int hi = 0; hi < 2; ++hi) {
-      const size_t per = size_t((N + 15) / 16) * ((2 * N + 3) / 4) * 64;
-      opsT[hi].assign(size_t(h->G) * 2 * per, 0.0);
-      for (int g = 1; g < h->G; ++g) {
-        const double* base = ho.ops[hi].data() + size_t(g) * 4 * nn;
-        const std::vector<double> tv = concat(base, base + nn);
-        const std::vector<double> te = concat(base + 2 * nn, base + 3 * nn);
-        std::copy(tv.begin(), tv.end(), opsT[hi].begin() + size_t(g) * 2 * per);
-        std::copy(te.begin(), te.end(), opsT[hi].begin() + size_t(g) * 2 * per + per);
+  const int He = (N + 1) / 2, Ho = N / 2, Fe = He + 1, Fo = Ho + 1;
+  auto ntile = [](int r, int k) { return size_t((r + 15) / 16) * ((k + 3) / 4) * 64; };
+  const size_t per_e = ntile(He, 2 * He), per_o = ntile(Ho, 2 * Ho);
+  h->op_group_stride = 2 * (per_e + per_o);
+  // [A | B] restricted to one parity (n x 2n), tiled
+  auto pair_block = [&](const double* A, const double* B, bool even) {
+    const int n = even ? He : Ho;
+    const std::vector<double> a = half_block(A, n, N, N, even);
+    const std::vector<double> b = half_block(B, n, N, N, even);
+    std::vector<double> cat(size_t(n) * 2 * n);
+    for (int r = 0; r < n; ++r)
+      for (int k = 0; k < n; ++k) {
+        cat[size_t(r) * 2 * n + k] = a[size_t(r) * n + k];
+        cat[size_t(r) * 2 * n + n + k] = b[size_t(r) * n + k];
       }
-      meanT[hi] = concat(ho.mean_ops[hi].data(), ho.mean_ops[hi].data() + nn);
+    return tile_for_mfma(cat.data(), n, 2 * n, 2 * n);
+  };
+  // halves of an interior vector: even (He) then odd (Ho)
+  auto halves = [&](const std::vector<double>& x) {
+    std::vector<double> out(size_t(N), 0.0);
+    for (int k = 0; k < He; ++k) out[k] = (k < Ho) ? 0.5 * (x[k] + x[N - 1 - k]) : x[k];
+    for (int k = 0; k < Ho; ++k) out[He + k] = 0.5 * (x[k] - x[N - 1 - k]);
+    return out;
+  };
+  std::vector<double> opsT[2], meanT[2], lift_h[2], green_h[2];
+  const size_t nn = size_t(N) * N;
+  for (int hi = 0; hi < 2; ++hi) {
+    opsT[hi].assign(size_t(h->G) * h->op_group_stride, 0.0);
+    for (int g = 1; g < h->G; ++g) {
+      const double* base = ho.ops[hi].data() + size_t(g) * 4 * nn;
+      auto dst = opsT[hi].begin() + size_t(g) * h->op_group_stride;
+      for (int blk = 0; blk < 4; ++blk) {  // v even, v odd, eta even, eta odd
+        const double* A = base + (blk < 2 ? 0 : 2 * nn);
+        const std::vector<double> t = pair_block(A, A + nn, (blk & 1) == 0);
+        dst = std::copy(t.begin(), t.end(), dst);
+      }
     }
+    meanT[hi] = pair_block(ho.mean_ops[hi].data(), ho.mean_ops[hi].data() + nn, true);
+    const std::vector<double> mo = pair_block(ho.mean_ops[hi].data(), ho.mean_ops[hi].data() + nn, false);
+    meanT[hi].insert(meanT[hi].end(), mo.begin(), mo.end());
+    lift_h[hi] = halves(ho.lift[hi]);
+    green_h[hi] = halves(ho.green[hi]);
   }
-  const std::vector<double> D1intT = tile_for_mfma(ho.D1.data() + My, N, My, My);
-  const std::vector<double> D1cT = tile_for_mfma(ho.D1c.data(), My, N, N);
-  const std::vector<double> D1T = tile_for_mfma(ho.D1.data(), My, My, My);
+  // derivative halves: even input -> odd output and odd input -> even output
+  auto dhalf = [&](const double* M, int rows_out, int Cn, int ldm, bool even_in) {
+    const std::vector<double> b = half_block(M, rows_out, Cn, ldm, even_in);
+    const int ncol = even_in ? (Cn + 1) / 2 : Cn / 2;
+    return tile_for_mfma(b.data(), rows_out, ncol, ncol);
+  };
+  const double* D1int = ho.D1.data() + My;  // interior rows of D1
+  const std::vector<double> D1intT_e = dhalf(D1int, Ho, My, My, true);
+  const std::vector<double> D1intT_o = dhalf(D1int, He, My, My, false);
+  const std::vector<double> D1cT_e = dhalf(ho.D1c.data(), Fo, N, N, true);
+  const std::vector<double> D1cT_o = dhalf(ho.D1c.data(), Fe, N, N, false);
+  const std::vector<double> D1T_e = dhalf(ho.D1.data(), Fo, My, My, true);
+  const std::vector<double> D1T_o = dhalf(ho.D1.data(), Fe, My, My, false);
+  // Clenshaw-Curtis weights over node pairs (the weights are symmetric)
+  std::vector<double> ccw_h(size_t(Fe), 0.0);
+  for (int k = 0; k < Fe; ++k) ccw_h[k] = k < Fo ? 2.0 * ho.ccw[k] : ho.ccw[k];
   for (int hi = 0; hi < 2; ++hi) {
     ALLOC(h->opsT[hi], opsT[hi].size());
     ALLOC(h->meanT[hi], meanT[hi].size());
-    ALLOC(h->lift[hi], ho.lift[hi].size());
-    ALLOC(h->green[hi], ho.green[hi].size());
+    ALLOC(h->lift_h[hi], lift_h[hi].size());
+    ALLOC(h->green_h[hi], green_h[hi].size());
   }
-  ALLOC(h->D1intT, D1intT.size());
-  ALLOC(h->D1cT, D1cT.size());
-  ALLOC(h->D1T, D1T.size());
+  ALLOC(h->D1intT_e, D1intT_e.size());
+  ALLOC(h->D1intT_o, D1intT_o.size());
+  ALLOC(h->D1cT_e, D1cT_e.size());
+  ALLOC(h->D1cT_o, D1cT_o.size());
+  ALLOC(h->D1T_e, D1T_e.size());
+  ALLOC(h->D1T_o, D1T_o.size());
+  ALLOC(h->ccw_h, ccw_h.size());
   ALLOC(h->D1, ho.D1.size());
   ALLOC(h->ccw, ho.ccw.size());
   ALLOC(h->gamma, size_t(h->E));
@@ -400,12 +526,16 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   for (int hi = 0; hi < 2; ++hi) {
     ok &= up(h->opsT[hi], opsT[hi]) == hipSuccess;
     ok &= up(h->meanT[hi], meanT[hi]) == hipSuccess;
-    ok &= up(h->lift[hi], ho.lift[hi]) == hipSuccess;
-    ok &= up(h->green[hi], ho.green[hi]) == hipSuccess;
+    ok &= up(h->lift_h[hi], lift_h[hi]) == hipSuccess;
+    ok &= up(h->green_h[hi], green_h[hi]) == hipSuccess;
   }
-  ok &= up(h->D1intT, D1intT) == hipSuccess;
-  ok &= up(h->D1cT, D1cT) == hipSuccess;
-  ok &= up(h->D1T, D1T) == hipSuccess;
+  ok &= up(h->D1intT_e, D1intT_e) == hipSuccess;
+  ok &= up(h->D1intT_o, D1intT_o) == hipSuccess;
+  ok &= up(h->D1cT_e, D1cT_e) == hipSuccess;
+  ok &= up(h->D1cT_o, D1cT_o) == hipSuccess;
+  ok &= up(h->D1T_e, D1T_e) == hipSuccess;
+  ok &= up(h->D1T_o, D1T_o) == hipSuccess;
+  ok &= up(h->ccw_h, ccw_h) == hipSuccess;
   ok &= up(h->D1, ho.D1) == hipSuccess;
   ok &= up(h->ccw, ho.ccw) == hipSuccess;
   // laminar state, zero history
@@ -439,8 +569,65 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   return DNS_OK;
 }
 
+int dns_create_grouped(const dns_group* groups, int ngroups, dns_handle** out) {
+  if (!out) return fail(nullptr, DNS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!groups || ngroups < 1 || ngroups > DNS_MAX_GROUPS)
+    return fail(nullptr, DNS_E_INVALID, "need 1 <= ngroups <= DNS_MAX_GROUPS and a group array");
+  dns_handle* h = new dns_handle();
+  auto bail = [&](int code, const std::string& msg) {
+    free_all(h);
+    delete h;
+    return fail(nullptr, code, msg);
+  };
+  int total = 0;
+  for (int g = 0; g < ngroups; ++g) {
+    const dns_group& q = groups[g];
+    dns_handle* sh = nullptr;
+    const int rc = dns_create(&q.g, q.Re, q.Nx, q.Ny, q.Nz, q.members, q.dt, &sh);
+    if (rc) return bail(rc, "group " + std::to_string(g) + ": " + g_thread_err);
+    sh->parent = h;
+    h->sub.push_back(sh);
+    h->sub_base.push_back(total);
+    total += q.members;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+      return bail(DNS_E_HIP, "hipEventCreate");
+    h->join.push_back(ev);
+  }
+  if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess)
+    return bail(DNS_E_HIP, "hipEventCreate");
+  if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(DNS_E_HIP, "hipStreamCreate");
+  h->stream = h->own_stream;
+  h->E = total;
+  *out = h;
+  return DNS_OK;
+}
+
+int dns_group_handle(dns_handle* h, int group, dns_handle** out) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  if (!out) return fail(h, DNS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!h->grouped()) return fail(h, DNS_E_INVALID, "not a grouped handle");
+  if (group < 0 || group >= int(h->sub.size())) return fail(h, DNS_E_INVALID, "group out of range");
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  *out = h->sub[group];
+  return DNS_OK;
+}
+
 int dns_set_option(dns_handle* h, int key, long long value) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS)) {
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    for (dns_handle* sh : h->sub) {
+      const int rc = dns_set_option(sh, key, value);
+      if (rc) return forward(h, sh, rc);
+    }
+    invalidate_graph(h);
+    return DNS_OK;
+  }
   switch (key) {
     case DNS_OPT_PRECISION:
       if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32)
@@ -469,6 +656,13 @@ int dns_set_option(dns_handle* h, int key, long long value) {
 
 int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    dns_handle* sh;
+    int m0;
+    const int rc = route(h, member0, count, &sh, &m0);
+    return rc ? rc : forward(h, sh, dns_set_state(sh, m0, count, s));
+  }
   if (!s || !s->v_hat || !s->eta_hat || !s->U00 || !s->W00)
     return fail(h, DNS_E_INVALID, "state view has NULL buffers");
   if (member0 < 0 || count < 1 || member0 + count > h->E)
@@ -512,6 +706,13 @@ int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s
 
 int dns_get_state(dns_handle* h, int member0, int count, dns_state_view* s) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    dns_handle* sh;
+    int m0;
+    const int rc = route(h, member0, count, &sh, &m0);
+    return rc ? rc : forward(h, sh, dns_get_state(sh, m0, count, s));
+  }
   if (!s || !s->v_hat || !s->eta_hat || !s->U00 || !s->W00)
     return fail(h, DNS_E_INVALID, "state view has NULL buffers");
   if (member0 < 0 || count < 1 || member0 + count > h->E)
@@ -536,9 +737,26 @@ int dns_get_state(dns_handle* h, int member0, int count, dns_state_view* s) {
 
 int dns_step(dns_handle* h, int nsteps) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
   if (nsteps < 0) return fail(h, DNS_E_INVALID, "nsteps must be >= 0");
   if (nsteps == 0) return DNS_OK;
-  if (!h->vel_fresh) {
+  if (h->grouped()) {
+    for (size_t g = 0; g < h->sub.size(); ++g) {
+      HIP_OR_FAIL(h, hipEventRecord(h->join[g], h->sub[g]->stream));
+      HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->join[g], 0));
+    }
+    bool stale = false;
+    for (dns_handle* sh : h->sub) stale |= !sh->vel_fresh;
+    if (stale) {
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      for (dns_handle* sh : h->sub) {
+        if (sh->vel_fresh) continue;
+        const int rc = refresh_velocities(sh);
+        if (rc) return forward(h, sh, rc);
+        HIP_OR_FAIL(h, hipStreamSynchronize(sh->stream));
+      }
+    }
+  } else if (!h->vel_fresh) {
     int rc = refresh_velocities(h);
     if (rc) return rc;
   }
@@ -550,18 +768,32 @@ int dns_step(dns_handle* h, int nsteps) {
     for (int n = 0; n < nsteps; ++n) HIP_OR_FAIL(h, hipGraphLaunch(h->gexec, h->stream));
   } else {
     for (int n = 0; n < nsteps; ++n) {
-      int rc = enqueue_step(h);
+      int rc = enqueue_any(h);
       if (rc) return rc;
     }
   }
   h->steps += nsteps;
   if (h->stats_on) h->samples += nsteps;
+  for (dns_handle* sh : h->sub) {
+    sh->steps += nsteps;
+    if (sh->stats_on) sh->samples += nsteps;
+  }
   return DNS_OK;
 }
 
 int dns_sync(dns_handle* h) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (h->grouped()) {
+    int out = DNS_OK;
+    for (dns_handle* sh : h->sub) {
+      const int rc = dns_sync(sh);
+      if (rc == DNS_E_NONFINITE) out = rc;
+      else if (rc) return forward(h, sh, rc);
+    }
+    return out ? fail(h, out, "a member produced a non-finite value") : DNS_OK;
+  }
   const int any = any_failed(h, nullptr);
   if (any < 0) return fail(h, DNS_E_HIP, "reading failure flags");
   if (any) return fail(h, DNS_E_NONFINITE, "a member produced a non-finite value");
@@ -570,7 +802,37 @@ int dns_sync(dns_handle* h) {
 
 int dns_stats(dns_handle* h, dns_stats_out* o) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
   if (!o) return fail(h, DNS_E_INVALID, "output is NULL");
+  if (h->grouped()) {
+    if (o->U || o->W || o->urms || o->vrms || o->wrms || o->uv)
+      return fail(h, DNS_E_INVALID,
+                  "profiles of a grouped handle differ per group: read them from dns_group_handle");
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    int out = DNS_OK;
+    for (size_t g = 0; g < h->sub.size(); ++g) {
+      const int b = h->sub_base[g];
+      auto at = [b](double* p) { return p ? p + b : nullptr; };
+      dns_stats_out so{};
+      so.energy = at(o->energy);
+      so.dissipation = at(o->dissipation);
+      so.power = at(o->power);
+      so.flux = at(o->flux);
+      so.gamma = at(o->gamma);
+      so.div_max = at(o->div_max);
+      so.tau_lower = at(o->tau_lower);
+      so.tau_upper = at(o->tau_upper);
+      so.failed = o->failed ? o->failed + b : nullptr;
+      const int rc = dns_stats(h->sub[g], &so);
+      if (rc == DNS_E_NONFINITE) out = rc;
+      else if (rc) return forward(h, h->sub[g], rc);
+    }
+    o->tau_w = 0.0;
+    o->re_tau = 0.0;
+    o->samples = h->sub[0]->samples;
+    o->steps = h->steps;
+    return out ? fail(h, out, "a member produced a non-finite value") : DNS_OK;
+  }
   // fresh diagnostics of the current state
   HIP_OR_FAIL(h, hipMemsetAsync(h->divmax, 0, sizeof(unsigned long long) * h->E, h->stream));
   int rc = refresh_velocities(h);
@@ -641,6 +903,16 @@ int dns_stats(dns_handle* h, dns_stats_out* o) {
 
 int dns_stats_reset(dns_handle* h) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    for (dns_handle* sh : h->sub) {
+      const int rc = dns_stats_reset(sh);
+      if (rc) return forward(h, sh, rc);
+    }
+    h->samples = 0;
+    return DNS_OK;
+  }
   HIP_OR_FAIL(h, hipMemsetAsync(h->acc, 0, (size_t(NPA) * h->My * h->E + 2 * h->E) * sizeof(double), h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   h->samples = 0;
@@ -648,10 +920,8 @@ int dns_stats_reset(dns_handle* h) {
 }
 
 void dns_destroy(dns_handle* h) {
-  if (!h) return;
-  hipStreamSynchronize(h->stream);
-  free_all(h);
-  delete h;
+  if (!h || h->parent) return;  // a group's handle belongs to its grouped handle
+  destroy_one(h);
 }
 
 const char* dns_last_error(const dns_handle* h) {
@@ -660,6 +930,8 @@ const char* dns_last_error(const dns_handle* h) {
 
 int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) return fail(h, DNS_E_INVALID, "call this on a group's handle (dns_group_handle)");
   int rc = refresh_velocities(h);
   if (rc) return rc;
   HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
@@ -696,6 +968,8 @@ int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
 
 int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) return fail(h, DNS_E_INVALID, "call this on a group's handle (dns_group_handle)");
   if (nreps < 1) return fail(h, DNS_E_INVALID, "nreps must be >= 1");
   if (!h->vel_fresh) {
     int rc = refresh_velocities(h);

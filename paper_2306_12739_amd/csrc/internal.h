@@ -50,15 +50,21 @@ struct ModeArgs {
   void* vel;          // complex VT [5][My][E][K] (written)
   const void* nl;     // complex VT [3][My][E][K] (read)
   const double* means;  // [2][My][E]
-  // operators, pre-tiled for v_mfma_f64_16x16x4f64 (see tile_for_mfma)
-  const double* opsT;   // per group: [A_v | B_v] then [A_eta | B_eta], each N x 2N
-  const double* meanT;  // [A_U | B_U], N x 2N
-  const double* D1intT; // D1[1:My-1, :], N x My
-  const double* D1cT;   // D1c, My x N
-  const double* D1T;    // D1, My x My
-  const double* lift;   // [N]
-  const double* green;  // [N]
-  const double* ccw;    // [My] Clenshaw-Curtis weights
+  // operators, split by y parity and pre-tiled for v_mfma_f64_16x16x4f64 (see
+  // tile_for_mfma): He = ceil(N/2), Ho = floor(N/2), Fe = He + 1, Fo = Ho + 1
+  const double* opsT;      // per group: [A_v|B_v] even (He x 2He), odd (Ho x 2Ho),
+                           // then [A_eta|B_eta] even, odd
+  size_t op_group_stride;  // doubles per group
+  const double* meanT;     // [A_U|B_U] even, odd
+  const double* D1intT_e;  // D1 interior rows: even full half -> odd interior half (Ho x Fe)
+  const double* D1intT_o;  // odd full half -> even interior half (He x Fo)
+  const double* D1cT_e;    // D1c: even interior half -> odd full half (Fo x He)
+  const double* D1cT_o;    // odd interior half -> even full half (Fe x Ho)
+  const double* D1T_e;     // D1: even full half -> odd full half (Fo x Fe)
+  const double* D1T_o;     // odd full half -> even full half (Fe x Fo)
+  const double* lift_h;    // [N]: even half (He) then odd half (Ho) of the Couette lift
+  const double* green_h;   // [N]: halves of the pressure-gradient response
+  const double* ccw_h;     // [Fe]: Clenshaw-Curtis weights summed over node pairs
   // per-member outputs
   double* gamma;        // [E]
   int* failed;          // [E]
@@ -82,6 +88,12 @@ void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR);
 // (rt, kt), rt < ceil(R/16), kt < ceil(Kd/4), is 64 consecutive values with
 // lane l holding M[16 rt + l % 16][4 kt + l / 16] (zero outside the matrix).
 std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm);
+
+// Half-size block of a matrix M (row stride ldm, Cn columns) for inputs of one
+// y parity: columns k < ceil(Cn/2) (even) or floor(Cn/2) (odd) hold
+// M[i][k] +/- M[i][Cn-1-k] (the centre column alone for even, odd Cn), rows
+// i < rows_out are the first-half rows of M.
+std::vector<double> half_block(const double* M, int rows_out, int Cn, int ldm, bool even_in);
 
 // layout transposes between the host state layout and the device layout
 hipError_t launch_state_to_device(const double* host_layout_dev, double* dev, int E0, int count,

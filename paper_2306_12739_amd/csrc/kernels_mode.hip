@@ -15,13 +15,20 @@
 //  * Eqs. (U00), (W00) with the Couette wall lift and, for the channel, a
 //    pressure gradient gamma that holds the bulk flux at its target.
 //
-// Every y contraction Y = M X is a real matrix (an operator or a Chebyshev
-// derivative) times real columns (re/im of every (mode, member) pair) and runs
-// on the FP64 matrix cores: v_mfma_f64_16x16x4f64, one 16x16 output tile per
-// wavefront, K in steps of 4.  Operators are stored pre-tiled in the MFMA A
-// lane order (tile (rt, kt) = 64 consecutive doubles, lane l holding
-// M[16 rt + l % 16][4 kt + l / 16]) so each A fragment is one coalesced 512 B
-// load; X lives in LDS as [k][column] so each B fragment is four 128 B rows.
+// y-parity split.  The Gauss-Lobatto grid is symmetric under y -> -y (node j
+// <-> My-1-j).  Every CN operator commutes with that reflection and D1, D1c
+// anticommute with it, so in the basis of even halves e[k] = (x[k] +
+// x[n-1-k])/2 and odd halves o[k] = (x[k] - x[n-1-k])/2 each product splits
+// into two half-size products (even -> even and odd -> odd for the operators,
+// even -> odd and odd -> even for the derivatives).  This halves the matrix
+// work and the operator stream; the pointwise steps act on halves unchanged
+// because their coefficients do not depend on y.
+//
+// Every half-size contraction Y = M X runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64, one 16x16 output tile per wavefront, K in steps of
+// 4).  Matrices are stored pre-tiled in the MFMA A lane order (tile (rt, kt) =
+// 64 consecutive doubles, lane l holding M[16 rt + l % 16][4 kt + l / 16]), so
+// each A fragment is one coalesced 512 B load; X lives in LDS as [k][column].
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -43,7 +50,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Y = M X over every output tile of this workgroup; store(row, col, value) is
 // called once per element with row < 16 RT, col < 16 CT (the caller ignores
-// padding rows).  M: tiled operator (RT x KT tiles), X: LDS, row stride ldx.
+// padding rows).  M: tiled matrix with K = 4 KT columns (zero padded),
+// X: LDS, row stride ldx, at least 4 KT finite rows.
 // D layout of v_mfma_f64_16x16x4f64: lane l, register r -> row l/16 + 4r, col l%16.
 template <class Store>
 __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int RT, int KT,
@@ -82,16 +90,21 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 
 }  // namespace
 
-// LDS (doubles, row stride CRP = real columns padded to 16):
-//   S  [SR][CRP]  v-solve stack [v0; -h dt F_c], later eta (rows 0..My-1)
-//   S2 [SR][CRP]  eta-solve stack [eta0; -h dt G_c], later dv/dy then u
-//   T  [TR][CRP]  Q = i kx N_u + i kz N_w, later v (rows 0..My-1)
-// SR >= max(4 KT(2N), My), TR >= 4 KT(My); padding rows are zero.
+// Half sizes: interior N = My - 2 splits into He = ceil(N/2) even and Ho =
+// floor(N/2) odd rows; the full grid into Fe = He + 1 and Fo = Ho + 1 (the
+// wall pair adds one row to each parity).
+//
+// LDS buffers (doubles, row stride CRP = real columns padded to 16):
+//   full-half layout FH : rows [0, Fe) even, [Fe, My) odd; row 0 / Fe = walls
+//   S  : solve stack [v0_e; F'_e; v0_o; F'_o] (interior halves), later eta (FH)
+//   S2 : solve stack [eta0_e; G'_e; eta0_o; G'_o], later dv/dy, u, dw/dy (FH)
+//   T  : Q = i kx N_u + i kz N_w (FH), later v (FH), later du/dy (FH)
 template <typename VT>
 __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int My = a.My, N = a.N, K = a.K, E = a.E, NZ = a.NZ, P = a.P, ET = a.ET;
+  const int He = (N + 1) / 2, Ho = N / 2, Fe = He + 1, Fo = Ho + 1;
   const int C = 2 * ET;           // complex columns: (slot, member)
   const int CRP = a.CRP;          // real columns, padded to 16
   const int CT = CRP / 16;
@@ -112,9 +125,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   const int s = a.stage;
   const double hdt = a.hdt;
   const size_t KE = size_t(K) * E;
+  const size_t FS = 2 * size_t(My) * KE;  // stage-buffer field stride (VT units)
 
-  // column c -> (slot, member); real column 2c (re), 2c + 1 (im)
-  auto col_slot = [&](int c) { return c / ET; };
   auto col_member = [&](int c) { return tile * ET + (c - (c / ET) * ET); };
   auto col_valid = [&](int c) {
     const int sl = c / ET;
@@ -122,51 +134,95 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   };
   auto col_mode = [&](int c) { return nx * NZ + (c / ET == 0 ? az : NZ - az); };
   auto col_kz = [&](int c) { return (c / ET == 0 ? 1.0 : -1.0) * a.kzs * az; };
+  // stage-buffer element (node j, column c) in VT units
+  auto sb = [&](int j, int c) { return 2 * ((size_t(j) * E + col_member(c)) * K + col_mode(c)); };
+  // state element (interior node i in [0, N), column c)
+  auto st = [&](int i, int c) { return 2 * ((size_t(col_mode(c)) * N + i) * E + col_member(c)); };
   const double kx = a.kxs * nx;
 
-  // zero all buffers (padding rows and columns must hold zeros)
+  // zero all buffers once (padding rows and columns must hold finite zeros)
   for (int q = tid; q < (2 * SR + TR) * CRP; q += kNT) smem[q] = 0.0;
   __syncthreads();
 
-  const int RTn = (N + 15) / 16, RTm = (My + 15) / 16;
-  const int KT2n = (2 * N + 3) / 4, KTm = (My + 3) / 4, KTn = (N + 3) / 4;
+  // tile counts of the half-size matrices
+  const int RTe = (He + 15) / 16, RTo = (Ho + 15) / 16, RFe = (Fe + 15) / 16, RFo = (Fo + 15) / 16;
+  const int KSe = (2 * He + 3) / 4, KSo = (2 * Ho + 3) / 4;
+  const int KFe = (Fe + 3) / 4, KFo = (Fo + 3) / 4, KHe = (He + 3) / 4, KHo = (Ho + 3) / 4;
+
+  // write the FH pair k of buffer B (re/im columns 2c, 2c+1) to stage field f
+  auto write_pair = [&](const double* B, int k, int c, int f) {
+    const double er = B[k * CRP + 2 * c], ei = B[k * CRP + 2 * c + 1];
+    if (k < Fo) {
+      const double orr = B[(Fe + k) * CRP + 2 * c], oi = B[(Fe + k) * CRP + 2 * c + 1];
+      st_c(vel + f * FS + sb(k, c), er + orr, ei + oi);
+      st_c(vel + f * FS + sb(My - 1 - k, c), er - orr, ei - oi);
+    } else {
+      st_c(vel + f * FS + sb(k, c), er, ei);
+    }
+  };
 
   if (!mean_group) {
     // ===================== fluctuation modes (k^2 > 0) =====================
     if (s >= 0) {
-      for (int q = tid; q < My * C; q += kNT) {
-        const int i = q / C, c = q - i * C;
+      // Q on every node (FH), -k^2 N_v and G on interior nodes (solve stacks)
+      for (int q = tid; q < Fe * C; q += kNT) {
+        const int k = q / C, c = q - k * C;
         if (!col_valid(c)) continue;
-        const size_t off = 2 * ((size_t(i) * E + col_member(c)) * K + col_mode(c));
-        const size_t fs = 2 * size_t(My) * KE;
         const double kz = col_kz(c), k2 = kx * kx + kz * kz;
-        const double nur = nl[off], nui = nl[off + 1];
-        const double nvr = nl[off + fs], nvi = nl[off + fs + 1];
-        const double nwr = nl[off + 2 * fs], nwi = nl[off + 2 * fs + 1];
+        const bool pair = k < Fo;
+        const size_t o1 = sb(k, c), o2 = sb(My - 1 - k, c);
+        double he[6], ho[6];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            const double x1 = nl[f * FS + o1 + ri];
+            const double x2 = pair ? double(nl[f * FS + o2 + ri]) : x1;
+            he[2 * f + ri] = 0.5 * (x1 + x2);
+            ho[2 * f + ri] = 0.5 * (x1 - x2);
+          }
+        }
         // Q = i kx N_u + i kz N_w
-        T[i * CRP + 2 * c] = -(kx * nui + kz * nwi);
-        T[i * CRP + 2 * c + 1] = kx * nur + kz * nwr;
-        if (i >= 1 && i < My - 1) {
-          // -k^2 N_v into the lower half of S; G = i kz N_u - i kx N_w into S2
-          S[(N + i - 1) * CRP + 2 * c] = -k2 * nvr;
-          S[(N + i - 1) * CRP + 2 * c + 1] = -k2 * nvi;
-          S2[(N + i - 1) * CRP + 2 * c] = -(kz * nui - kx * nwi);
-          S2[(N + i - 1) * CRP + 2 * c + 1] = kz * nur - kx * nwr;
+        T[k * CRP + 2 * c] = -(kx * he[1] + kz * he[5]);
+        T[k * CRP + 2 * c + 1] = kx * he[0] + kz * he[4];
+        if (pair) {
+          T[(Fe + k) * CRP + 2 * c] = -(kx * ho[1] + kz * ho[5]);
+          T[(Fe + k) * CRP + 2 * c + 1] = kx * ho[0] + kz * ho[4];
+        }
+        if (k >= 1) {
+          const int kk = k - 1;  // interior half index
+          S[(He + kk) * CRP + 2 * c] = -k2 * he[2];
+          S[(He + kk) * CRP + 2 * c + 1] = -k2 * he[3];
+          S2[(He + kk) * CRP + 2 * c] = -(kz * he[1] - kx * he[5]);
+          S2[(He + kk) * CRP + 2 * c + 1] = kz * he[0] - kx * he[4];
+          if (kk < Ho) {
+            S[(2 * He + Ho + kk) * CRP + 2 * c] = -k2 * ho[2];
+            S[(2 * He + Ho + kk) * CRP + 2 * c + 1] = -k2 * ho[3];
+            S2[(2 * He + Ho + kk) * CRP + 2 * c] = -(kz * ho[1] - kx * ho[5]);
+            S2[(2 * He + Ho + kk) * CRP + 2 * c + 1] = kz * ho[0] - kx * ho[4];
+          }
         }
       }
       __syncthreads();
-      // F = -k^2 N_v - D1 Q on interior rows (D1int = D1[1:My-1, :])
-      mfma_contract(a.D1intT, RTn, KTm, T, CRP, CT, [&](int r, int cc, double v) {
-        if (r < N) S[(N + r) * CRP + cc] -= v;
+      // F = -k^2 N_v - D1 Q: odd F from even Q, even F from odd Q
+      mfma_contract(a.D1intT_e, RTo, KFe, T, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
+      });
+      mfma_contract(a.D1intT_o, RTe, KFo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < He) S[(He + r) * CRP + cc] -= v;
       });
       __syncthreads();
-      // RK3 combination, history, -h dt scaling; v0 and eta0 into the stacks
+      // RK3 combination on halves (history kept in half layout); v0, eta0 halves
       for (int q = tid; q < N * C; q += kNT) {
-        const int ii = q / C, c = q - ii * C;
+        const int hr = q / C, c = q - hr * C;
         if (!col_valid(c)) continue;
-        const size_t so = 2 * ((size_t(col_mode(c)) * N + ii) * E + col_member(c));
-        double Fr = S[(N + ii) * CRP + 2 * c], Fi = S[(N + ii) * CRP + 2 * c + 1];
-        double Gr = S2[(N + ii) * CRP + 2 * c], Gi = S2[(N + ii) * CRP + 2 * c + 1];
+        const bool even = hr < He;
+        const int kk = even ? hr : hr - He;
+        const int rowF = even ? He + kk : 2 * He + Ho + kk;
+        const int rowX = even ? kk : 2 * He + kk;
+        double Fr = S[rowF * CRP + 2 * c], Fi = S[rowF * CRP + 2 * c + 1];
+        double Gr = S2[rowF * CRP + 2 * c], Gi = S2[rowF * CRP + 2 * c + 1];
+        const size_t so = st(hr, c);
         double* hf = a.hF + so;
         double* hg = a.hG + so;
         if (s == 0) {
@@ -182,48 +238,62 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
           Fr = (hf[0] + Fr) * (1.0 / 6.0); Fi = (hf[1] + Fi) * (1.0 / 6.0);
           Gr = (hg[0] + Gr) * (1.0 / 6.0); Gi = (hg[1] + Gi) * (1.0 / 6.0);
         }
-        S[(N + ii) * CRP + 2 * c] = -hdt * Fr;
-        S[(N + ii) * CRP + 2 * c + 1] = -hdt * Fi;
-        S2[(N + ii) * CRP + 2 * c] = -hdt * Gr;
-        S2[(N + ii) * CRP + 2 * c + 1] = -hdt * Gi;
-        S[ii * CRP + 2 * c] = a.v[so];
-        S[ii * CRP + 2 * c + 1] = a.v[so + 1];
-        S2[ii * CRP + 2 * c] = a.eta[so];
-        S2[ii * CRP + 2 * c + 1] = a.eta[so + 1];
+        S[rowF * CRP + 2 * c] = -hdt * Fr;
+        S[rowF * CRP + 2 * c + 1] = -hdt * Fi;
+        S2[rowF * CRP + 2 * c] = -hdt * Gr;
+        S2[rowF * CRP + 2 * c + 1] = -hdt * Gi;
+        // state halves from interior nodes kk and N-1-kk
+        const size_t s1 = st(kk, c), s2 = st(N - 1 - kk, c);
+        const double sg = even ? 1.0 : -1.0;
+        const bool center = even && kk == Ho;  // only when N is odd
+        const double vr = center ? a.v[s1] : 0.5 * (a.v[s1] + sg * a.v[s2]);
+        const double vi = center ? a.v[s1 + 1] : 0.5 * (a.v[s1 + 1] + sg * a.v[s2 + 1]);
+        const double er = center ? a.eta[s1] : 0.5 * (a.eta[s1] + sg * a.eta[s2]);
+        const double ei = center ? a.eta[s1 + 1] : 0.5 * (a.eta[s1 + 1] + sg * a.eta[s2 + 1]);
+        S[rowX * CRP + 2 * c] = vr;
+        S[rowX * CRP + 2 * c + 1] = vi;
+        S2[rowX * CRP + 2 * c] = er;
+        S2[rowX * CRP + 2 * c + 1] = ei;
       }
       __syncthreads();
-      const double* opg = a.opsT + size_t(g) * 2 * RTn * KT2n * 64;
-      // v = [A_v | B_v] [v0; -h dt F_c] -> T rows 1..N (Q no longer needed;
-      // its wall rows 0 and My-1 must read as v = 0 later)
+      const double* opve = a.opsT + size_t(g) * a.op_group_stride;
+      const double* opvo = opve + size_t(RTe) * KSe * 64;
+      const double* opee = opvo + size_t(RTo) * KSo * 64;
+      const double* opeo = opee + size_t(RTe) * KSe * 64;
+      // v halves -> T (FH, interior rows from 1); the wall rows read as v = 0
       for (int q = tid; q < CRP; q += kNT) {
         T[q] = 0.0;
-        T[(My - 1) * CRP + q] = 0.0;
+        T[Fe * CRP + q] = 0.0;
       }
-      mfma_contract(opg, RTn, KT2n, S, CRP, CT, [&](int r, int cc, double v) {
-        if (r < N) T[(1 + r) * CRP + cc] = v;
+      mfma_contract(opve, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+        if (r < He) T[(1 + r) * CRP + cc] = v;
+      });
+      mfma_contract(opvo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
       });
       __syncthreads();
-      // eta = [A_eta | B_eta] [eta0; -h dt G_c] -> S rows 1..N; S rows 0 and
-      // My-1 become the eta wall values (zero).  Rows beyond My keep finite
-      // stack data that only meets the zero padding columns of D1.
+      // eta halves -> S (FH); rows beyond My keep finite stack data that only
+      // meets zero padding columns of D1
       for (int q = tid; q < CRP; q += kNT) {
         S[q] = 0.0;
-        S[(My - 1) * CRP + q] = 0.0;
+        S[Fe * CRP + q] = 0.0;
       }
-      mfma_contract(opg + size_t(RTn) * KT2n * 64, RTn, KT2n, S2, CRP, CT, [&](int r, int cc, double v) {
-        if (r < N) S[(1 + r) * CRP + cc] = v;
+      mfma_contract(opee, RTe, KSe, S2, CRP, CT, [&](int r, int cc, double v) {
+        if (r < He) S[(1 + r) * CRP + cc] = v;
+      });
+      mfma_contract(opeo, RTo, KSo, S2 + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Ho) S[(Fe + 1 + r) * CRP + cc] = v;
       });
       __syncthreads();
       if (s == 2) {
-        // Hermitian projection of the n_x = 0 column: (0, nz) and (0, -nz)
+        // Hermitian projection of the n_x = 0 column: (0, nz) and (0, -nz);
+        // a per-node combination of two columns, so it acts on halves as is
         if (nx == 0 && az > 0) {
-          for (int q = tid; q < N * ET; q += kNT) {
-            const int ii = q / ET, c0 = q - ii * ET, c1 = c0 + ET;
-            const int i = ii + 1;
-            double* bufs[2] = {T, S};
+          for (int q = tid; q < My * ET; q += kNT) {
+            const int i = q / ET, c0 = q - i * ET, c1 = c0 + ET;
 #pragma unroll
             for (int bsel = 0; bsel < 2; ++bsel) {
-              double* B = bufs[bsel];
+              double* B = bsel == 0 ? T : S;
               const double ar = B[i * CRP + 2 * c0], ai = B[i * CRP + 2 * c0 + 1];
               const double br = B[i * CRP + 2 * c1], bi = B[i * CRP + 2 * c1 + 1];
               const double pr = 0.5 * (ar + br), pi = 0.5 * (ai - bi);
@@ -235,77 +305,140 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
           }
           __syncthreads();
         }
-        for (int q = tid; q < N * C; q += kNT) {
-          const int ii = q / C, c = q - ii * C;
+        // state: interior node pairs (kk, N-1-kk) from FH rows 1 + kk, Fe + 1 + kk
+        for (int q = tid; q < He * C; q += kNT) {
+          const int kk = q / C, c = q - kk * C;
           if (!col_valid(c)) continue;
-          const size_t so = 2 * ((size_t(col_mode(c)) * N + ii) * E + col_member(c));
-          a.v[so] = T[(ii + 1) * CRP + 2 * c];
-          a.v[so + 1] = T[(ii + 1) * CRP + 2 * c + 1];
-          a.eta[so] = S[(ii + 1) * CRP + 2 * c];
-          a.eta[so + 1] = S[(ii + 1) * CRP + 2 * c + 1];
+          const int re = 1 + kk, ro = Fe + 1 + kk;
+          const double ver = T[re * CRP + 2 * c], vei = T[re * CRP + 2 * c + 1];
+          const double eer = S[re * CRP + 2 * c], eei = S[re * CRP + 2 * c + 1];
+          const size_t s1 = st(kk, c);
+          if (kk < Ho) {
+            const double vor = T[ro * CRP + 2 * c], voi = T[ro * CRP + 2 * c + 1];
+            const double eor = S[ro * CRP + 2 * c], eoi = S[ro * CRP + 2 * c + 1];
+            const size_t s2 = st(N - 1 - kk, c);
+            const double v1r = ver + vor, v1i = vei + voi, v2r = ver - vor, v2i = vei - voi;
+            const double e1r = eer + eor, e1i = eei + eoi, e2r = eer - eor, e2i = eei - eoi;
+            a.v[s1] = v1r; a.v[s1 + 1] = v1i;
+            a.v[s2] = v2r; a.v[s2 + 1] = v2i;
+            a.eta[s1] = e1r; a.eta[s1 + 1] = e1i;
+            a.eta[s2] = e2r; a.eta[s2 + 1] = e2i;
+            // halves of the stored (rounded) values, formed exactly as a restart
+            // from this state forms them, so that a resumed run is bitwise equal
+            T[re * CRP + 2 * c] = 0.5 * (v1r + v2r);
+            T[re * CRP + 2 * c + 1] = 0.5 * (v1i + v2i);
+            T[ro * CRP + 2 * c] = 0.5 * (v1r - v2r);
+            T[ro * CRP + 2 * c + 1] = 0.5 * (v1i - v2i);
+            S[re * CRP + 2 * c] = 0.5 * (e1r + e2r);
+            S[re * CRP + 2 * c + 1] = 0.5 * (e1i + e2i);
+            S[ro * CRP + 2 * c] = 0.5 * (e1r - e2r);
+            S[ro * CRP + 2 * c + 1] = 0.5 * (e1i - e2i);
+          } else {
+            a.v[s1] = ver; a.v[s1 + 1] = vei;
+            a.eta[s1] = eer; a.eta[s1 + 1] = eei;
+          }
         }
       }
     } else {
-      // velocities of the stored state: v -> T rows 1..N, eta -> S rows 1..N
-      for (int q = tid; q < N * C; q += kNT) {
-        const int ii = q / C, c = q - ii * C;
+      // velocities of the stored state: v -> T (FH), eta -> S (FH)
+      for (int q = tid; q < He * C; q += kNT) {
+        const int kk = q / C, c = q - kk * C;
         if (!col_valid(c)) continue;
-        const size_t so = 2 * ((size_t(col_mode(c)) * N + ii) * E + col_member(c));
-        T[(ii + 1) * CRP + 2 * c] = a.v[so];
-        T[(ii + 1) * CRP + 2 * c + 1] = a.v[so + 1];
-        S[(ii + 1) * CRP + 2 * c] = a.eta[so];
-        S[(ii + 1) * CRP + 2 * c + 1] = a.eta[so + 1];
+        const size_t s1 = st(kk, c);
+        const int re = 1 + kk, ro = Fe + 1 + kk;
+        if (kk < Ho) {
+          const size_t s2 = st(N - 1 - kk, c);
+          T[re * CRP + 2 * c] = 0.5 * (a.v[s1] + a.v[s2]);
+          T[re * CRP + 2 * c + 1] = 0.5 * (a.v[s1 + 1] + a.v[s2 + 1]);
+          T[ro * CRP + 2 * c] = 0.5 * (a.v[s1] - a.v[s2]);
+          T[ro * CRP + 2 * c + 1] = 0.5 * (a.v[s1 + 1] - a.v[s2 + 1]);
+          S[re * CRP + 2 * c] = 0.5 * (a.eta[s1] + a.eta[s2]);
+          S[re * CRP + 2 * c + 1] = 0.5 * (a.eta[s1 + 1] + a.eta[s2 + 1]);
+          S[ro * CRP + 2 * c] = 0.5 * (a.eta[s1] - a.eta[s2]);
+          S[ro * CRP + 2 * c + 1] = 0.5 * (a.eta[s1 + 1] - a.eta[s2 + 1]);
+        } else {
+          T[re * CRP + 2 * c] = a.v[s1];
+          T[re * CRP + 2 * c + 1] = a.v[s1 + 1];
+          S[re * CRP + 2 * c] = a.eta[s1];
+          S[re * CRP + 2 * c + 1] = a.eta[s1 + 1];
+        }
       }
     }
     __syncthreads();
-    // ---- velocity recovery: dv/dy = D1c v -> S2 rows 0..My-1 ---------------
-    mfma_contract(a.D1cT, RTm, KTn, T + CRP, CRP, CT, [&](int r, int cc, double v) {
-      if (r < My) S2[r * CRP + cc] = v;
+    // ---- velocity recovery: dv/dy = D1c v (odd <- even, even <- odd) -> S2 FH
+    mfma_contract(a.D1cT_e, RFo, KHe, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
+    });
+    mfma_contract(a.D1cT_o, RFe, KHo, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Fe) S2[r * CRP + cc] = v;
     });
     __syncthreads();
     double dmax = 0.0;
-    for (int q = tid; q < My * C; q += kNT) {
-      const int i = q / C, c = q - i * C;
+    for (int q = tid; q < Fe * C; q += kNT) {
+      const int k = q / C, c = q - k * C;
       const double kz = col_kz(c), k2 = kx * kx + kz * kz;
       const double ik2 = k2 > 0.0 ? 1.0 / k2 : 0.0;
-      const double dr = S2[i * CRP + 2 * c], di = S2[i * CRP + 2 * c + 1];
-      const double er = S[i * CRP + 2 * c], ei = S[i * CRP + 2 * c + 1];
-      const double vr = T[i * CRP + 2 * c], vi = T[i * CRP + 2 * c + 1];
-      // u = (i kx dv - i kz eta) / k^2 ; w = (i kx eta + i kz dv) / k^2
-      const double ur = (-kx * di + kz * ei) * ik2, ui = (kx * dr - kz * er) * ik2;
-      const double wr = (-kx * ei - kz * di) * ik2, wi = (kx * er + kz * dr) * ik2;
-      S2[i * CRP + 2 * c] = ur;
-      S2[i * CRP + 2 * c + 1] = ui;
-      S[i * CRP + 2 * c] = wr;
-      S[i * CRP + 2 * c + 1] = wi;
+      const bool pair = k < Fo;
+      double uh[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, wh[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+      double dh[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        if (par == 1 && !pair) continue;
+        const int row = par == 0 ? k : Fe + k;
+        const double dr = S2[row * CRP + 2 * c], di = S2[row * CRP + 2 * c + 1];
+        const double er = S[row * CRP + 2 * c], ei = S[row * CRP + 2 * c + 1];
+        // u = (i kx dv - i kz eta) / k^2 ; w = (i kx eta + i kz dv) / k^2
+        const double ur = (-kx * di + kz * ei) * ik2, ui = (kx * dr - kz * er) * ik2;
+        const double wr = (-kx * ei - kz * di) * ik2, wi = (kx * er + kz * dr) * ik2;
+        S2[row * CRP + 2 * c] = ur;
+        S2[row * CRP + 2 * c + 1] = ui;
+        S[row * CRP + 2 * c] = wr;
+        S[row * CRP + 2 * c + 1] = wi;
+        uh[par][0] = ur; uh[par][1] = ui;
+        wh[par][0] = wr; wh[par][1] = wi;
+        dh[par][0] = dr; dh[par][1] = di;
+      }
       if (col_valid(c)) {
-        const size_t off = 2 * ((size_t(i) * E + col_member(c)) * K + col_mode(c));
-        const size_t fs = 2 * size_t(My) * KE;
-        st_c(vel + off, ur, ui);
-        st_c(vel + off + fs, vr, vi);
-        st_c(vel + off + 2 * fs, wr, wi);
-        // divergence i kx u + dv/dy + i kz w
-        const double xr = -kx * ui + dr - kz * wi, xi = kx * ur + di + kz * wr;
-        dmax = fmax(dmax, sqrt(xr * xr + xi * xi));
+        write_pair(T, k, c, 1);  // v
+        // u, w and the divergence i kx u + dv/dy + i kz w at both nodes
+        for (int side = 0; side < (pair ? 2 : 1); ++side) {
+          const double sg = side == 0 ? 1.0 : -1.0;
+          const int j = side == 0 ? k : My - 1 - k;
+          const double ur = uh[0][0] + sg * uh[1][0], ui = uh[0][1] + sg * uh[1][1];
+          const double wr = wh[0][0] + sg * wh[1][0], wi = wh[0][1] + sg * wh[1][1];
+          const double dr = dh[0][0] + sg * dh[1][0], di = dh[0][1] + sg * dh[1][1];
+          st_c(vel + 0 * FS + sb(j, c), ur, ui);
+          st_c(vel + 2 * FS + sb(j, c), wr, wi);
+          const double xr = -kx * ui + dr - kz * wi, xi = kx * ur + di + kz * wr;
+          dmax = fmax(dmax, sqrt(xr * xr + xi * xi));
+        }
       }
     }
     __syncthreads();
-    // du/dy = D1 u, dw/dy = D1 w -> velocity fields 3 and 4
-    auto store_y = [&](int f, const double* Xsrc) {
-      mfma_contract(a.D1T, RTm, KTm, Xsrc, CRP, CT, [&](int r, int cc, double v) {
-        const int c = cc >> 1;
-        if (r < My && c < C && col_valid(c)) {
-          const size_t off = 2 * (((size_t(f) * My + r) * E + col_member(c)) * K + col_mode(c));
-          vel[off + (cc & 1)] = VT(v);
-        }
-      });
-    };
-    store_y(3, S2);
-    store_y(4, S);
+    // du/dy = D1 u -> T (FH); then dw/dy = D1 w -> S2 (FH)
+    mfma_contract(a.D1T_e, RFo, KFe, S2, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Fo) T[(Fe + r) * CRP + cc] = v;
+    });
+    mfma_contract(a.D1T_o, RFe, KFo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Fe) T[r * CRP + cc] = v;
+    });
+    __syncthreads();
+    mfma_contract(a.D1T_e, RFo, KFe, S, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
+    });
+    mfma_contract(a.D1T_o, RFe, KFo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Fe) S2[r * CRP + cc] = v;
+    });
+    __syncthreads();
+    for (int q = tid; q < Fe * C; q += kNT) {
+      const int k = q / C, c = q - k * C;
+      if (!col_valid(c)) continue;
+      write_pair(T, k, c, 3);
+      write_pair(S2, k, c, 4);
+    }
     if (s == 2 || s < 0) {
       red[tid] = dmax;
       __syncthreads();
-      // per member: max over the threads that saw its columns
       if (tid < C && col_valid(tid)) {
         double mx = 0.0;
         for (int q = 0; q < kNT; ++q)
@@ -317,28 +450,46 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   }
 
   // ========================= mean profiles (0, 0) ===========================
-  // Real columns 2e (U or <uv> or E_U) and 2e + 1 (W or <wv> or E_W), e < ET;
-  // U and W share A_U, B_U (Eqs. (CN3), (CN4)).
-  const int NM = ET;  // members in this tile (slot 0 only)
+  // Real columns 2e (U, <uv>, E_U) and 2e + 1 (W, <wv>, E_W), e < ET; U and W
+  // share A_U, B_U (Eqs. (CN3), (CN4)), which commute with the reflection.
+  const int NM = ET;
   if (s >= 0) {
-    for (int q = tid; q < My * NM; q += kNT) {
-      const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+    // plane means (FH halves)
+    for (int q = tid; q < Fe * NM; q += kNT) {
+      const int k = q / NM, el = q - k * NM, e = tile * ET + el;
       if (e >= E) continue;
-      T[i * CRP + 2 * el] = a.means[(size_t(0) * My + i) * E + e];
-      T[i * CRP + 2 * el + 1] = a.means[(size_t(1) * My + i) * E + e];
+      const int j2 = My - 1 - k;
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+        const double x1 = a.means[(size_t(comp) * My + k) * E + e];
+        const double x2 = a.means[(size_t(comp) * My + j2) * E + e];
+        if (k < Fo) {
+          T[k * CRP + 2 * el + comp] = 0.5 * (x1 + x2);
+          T[(Fe + k) * CRP + 2 * el + comp] = 0.5 * (x1 - x2);
+        } else {
+          T[k * CRP + 2 * el + comp] = x1;
+        }
+      }
     }
     __syncthreads();
-    // E_U + E_W = -D1 (<uv>, <wv>) on interior rows -> S rows N..2N-1
-    mfma_contract(a.D1intT, RTn, KTm, T, CRP, CT, [&](int r, int cc, double v) {
-      if (r < N) S[(N + r) * CRP + cc] = -v;
+    // (E_U, E_W) = -D1 (<uv>, <wv>) on interior halves
+    mfma_contract(a.D1intT_e, RTo, KFe, T, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] = -v;
+    });
+    mfma_contract(a.D1intT_o, RTe, KFo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < He) S[(He + r) * CRP + cc] = -v;
     });
     __syncthreads();
     for (int q = tid; q < N * NM; q += kNT) {
-      const int ii = q / NM, el = q - ii * NM, e = tile * ET + el;
+      const int hr = q / NM, el = q - hr * NM, e = tile * ET + el;
       if (e >= E) continue;
-      double xu = S[(N + ii) * CRP + 2 * el], xw = S[(N + ii) * CRP + 2 * el + 1];
-      double* hu = a.hEU + size_t(ii) * E + e;
-      double* hw = a.hEW + size_t(ii) * E + e;
+      const bool even = hr < He;
+      const int kk = even ? hr : hr - He;
+      const int rowF = even ? He + kk : 2 * He + Ho + kk;
+      const int rowX = even ? kk : 2 * He + kk;
+      double xu = S[rowF * CRP + 2 * el], xw = S[rowF * CRP + 2 * el + 1];
+      double* hu = a.hEU + size_t(hr) * E + e;
+      double* hw = a.hEW + size_t(hr) * E + e;
       if (s == 0) {
         *hu = xu;
         *hw = xw;
@@ -352,27 +503,49 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
         xu = (*hu + xu) * (1.0 / 6.0);
         xw = (*hw + xw) * (1.0 / 6.0);
       }
-      S[(N + ii) * CRP + 2 * el] = hdt * xu;
-      S[(N + ii) * CRP + 2 * el + 1] = hdt * xw;
-      S[ii * CRP + 2 * el] = a.U[size_t(ii + 1) * E + e];
-      S[ii * CRP + 2 * el + 1] = a.W[size_t(ii + 1) * E + e];
+      S[rowF * CRP + 2 * el] = hdt * xu;
+      S[rowF * CRP + 2 * el + 1] = hdt * xw;
+      // interior nodes 1 + kk and My - 2 - kk of U0, W0
+      const size_t j1 = size_t(1 + kk) * E + e, j2 = size_t(My - 2 - kk) * E + e;
+      const bool center = even && kk == Ho;
+      const double sg = even ? 1.0 : -1.0;
+      S[rowX * CRP + 2 * el] = center ? a.U[j1] : 0.5 * (a.U[j1] + sg * a.U[j2]);
+      S[rowX * CRP + 2 * el + 1] = center ? a.W[j1] : 0.5 * (a.W[j1] + sg * a.W[j2]);
     }
     __syncthreads();
-    // (U_a, W) = [A_U | B_U] [(U0, W0); h dt (E_U,c, E_W,c)] -> T rows 1..N
-    mfma_contract(a.meanT, RTn, KT2n, S, CRP, CT, [&](int r, int cc, double v) {
-      if (r < N) T[(1 + r) * CRP + cc] = v;
+    // (U_a, W) halves = [A_U | B_U] halves -> T (FH)
+    const double* me = a.meanT;
+    const double* mo = me + size_t(RTe) * KSe * 64;
+    mfma_contract(me, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+      if (r < He) T[(1 + r) * CRP + cc] = v;
+    });
+    mfma_contract(mo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
     });
     __syncthreads();
-    // lift, bulk flux of the provisional U and gamma, one thread per member
+    // wall pair, lift on the interior halves
+    for (int q = tid; q < Fe * NM; q += kNT) {
+      const int k = q / NM, el = q - k * NM;
+      if (k == 0) {
+        T[2 * el] = 0.5 * (a.Ubot + a.Utop);
+        T[2 * el + 1] = 0.0;
+        T[Fe * CRP + 2 * el] = 0.5 * (a.Ubot - a.Utop);
+        T[Fe * CRP + 2 * el + 1] = 0.0;
+      } else {
+        T[k * CRP + 2 * el] += a.lift_h[k - 1];
+        if (k - 1 < Ho) T[(Fe + k) * CRP + 2 * el] += a.lift_h[He + k - 1];
+      }
+    }
+    __syncthreads();
+    // bulk flux of the provisional U (even half only) and gamma per member
     if (tid < NM) {
       const int el = tid, e = tile * ET + el;
       double gam = 0.0;
       if (a.poiseuille) {
-        double qa = a.ccw[0] * a.Ubot + a.ccw[My - 1] * a.Utop;
-        double wg = 0.0;
-        for (int i = 1; i < My - 1; ++i) {
-          qa += a.ccw[i] * (T[i * CRP + 2 * el] + a.lift[i - 1]);
-          wg += a.ccw[i] * a.green[i - 1];
+        double qa = 0.0, wg = 0.0;
+        for (int k = 0; k < Fe; ++k) {
+          qa += a.ccw_h[k] * T[k * CRP + 2 * el];
+          if (k >= 1) wg += a.ccw_h[k] * a.green_h[k - 1];
         }
         gam = (a.Qtarget - qa) / wg;
       }
@@ -380,67 +553,98 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       if (e < E) a.gamma[e] = gam;
     }
     __syncthreads();
-    for (int q = tid; q < My * NM; q += kNT) {
-      const int i = q / NM, el = q - i * NM;
-      if (i == 0) {
-        T[2 * el] = a.Ubot;
-        T[2 * el + 1] = 0.0;
-      } else if (i == My - 1) {
-        T[i * CRP + 2 * el] = a.Utop;
-        T[i * CRP + 2 * el + 1] = 0.0;
-      } else {
-        T[i * CRP + 2 * el] += a.lift[i - 1] + gam_s[el] * a.green[i - 1];
-      }
+    // gamma response is even (the green function is symmetric)
+    for (int q = tid; q < He * NM; q += kNT) {
+      const int kk = q / NM, el = q - kk * NM;
+      T[(1 + kk) * CRP + 2 * el] += gam_s[el] * a.green_h[kk];
     }
     __syncthreads();
     if (s == 2) {
-      for (int q = tid; q < My * NM; q += kNT) {
-        const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+      for (int q = tid; q < Fe * NM; q += kNT) {
+        const int k = q / NM, el = q - k * NM, e = tile * ET + el;
         if (e >= E) continue;
-        a.U[size_t(i) * E + e] = T[i * CRP + 2 * el];
-        a.W[size_t(i) * E + e] = T[i * CRP + 2 * el + 1];
+        const double ue = T[k * CRP + 2 * el], we = T[k * CRP + 2 * el + 1];
+        if (k < Fo) {
+          const double uo = T[(Fe + k) * CRP + 2 * el], wo = T[(Fe + k) * CRP + 2 * el + 1];
+          const double u1 = ue + uo, w1 = we + wo, u2 = ue - uo, w2 = we - wo;
+          a.U[size_t(k) * E + e] = u1;
+          a.W[size_t(k) * E + e] = w1;
+          a.U[size_t(My - 1 - k) * E + e] = u2;
+          a.W[size_t(My - 1 - k) * E + e] = w2;
+          // halves of the stored values, as a restart forms them
+          T[k * CRP + 2 * el] = 0.5 * (u1 + u2);
+          T[k * CRP + 2 * el + 1] = 0.5 * (w1 + w2);
+          T[(Fe + k) * CRP + 2 * el] = 0.5 * (u1 - u2);
+          T[(Fe + k) * CRP + 2 * el + 1] = 0.5 * (w1 - w2);
+        } else {
+          a.U[size_t(k) * E + e] = ue;
+          a.W[size_t(k) * E + e] = we;
+        }
       }
     }
   } else {
-    for (int q = tid; q < My * NM; q += kNT) {
-      const int i = q / NM, el = q - i * NM, e = tile * ET + el;
+    for (int q = tid; q < Fe * NM; q += kNT) {
+      const int k = q / NM, el = q - k * NM, e = tile * ET + el;
       if (e >= E) continue;
-      T[i * CRP + 2 * el] = a.U[size_t(i) * E + e];
-      T[i * CRP + 2 * el + 1] = a.W[size_t(i) * E + e];
+      const size_t j1 = size_t(k) * E + e, j2 = size_t(My - 1 - k) * E + e;
+      if (k < Fo) {
+        T[k * CRP + 2 * el] = 0.5 * (a.U[j1] + a.U[j2]);
+        T[k * CRP + 2 * el + 1] = 0.5 * (a.W[j1] + a.W[j2]);
+        T[(Fe + k) * CRP + 2 * el] = 0.5 * (a.U[j1] - a.U[j2]);
+        T[(Fe + k) * CRP + 2 * el + 1] = 0.5 * (a.W[j1] - a.W[j2]);
+      } else {
+        T[k * CRP + 2 * el] = a.U[j1];
+        T[k * CRP + 2 * el + 1] = a.W[j1];
+      }
     }
-    __syncthreads();
   }
-  // velocity fields of the (0, 0) mode: u = U, v = 0, w = W, du/dy, dw/dy
-  for (int q = tid; q < My * NM; q += kNT) {
-    const int i = q / NM, el = q - i * NM, e = tile * ET + el;
-    if (e >= E) continue;
-    const size_t off = 2 * ((size_t(i) * E + e) * K);
-    const size_t fs = 2 * size_t(My) * KE;
-    st_c(vel + off, T[i * CRP + 2 * el], 0.0);
-    st_c(vel + off + fs, 0.0, 0.0);
-    st_c(vel + off + 2 * fs, T[i * CRP + 2 * el + 1], 0.0);
-  }
-  mfma_contract(a.D1T, RTm, KTm, T, CRP, CT, [&](int r, int cc, double v) {
-    const int el = cc >> 1, e = tile * ET + el;
-    if (r < My && el < NM && e < E) {
-      const int f = 3 + (cc & 1);
-      const size_t off = 2 * (((size_t(f) * My + r) * E + e) * K);
-      st_c(vel + off, v, 0.0);
-    }
+  __syncthreads();
+  // (0,0) velocity fields: u = U, v = 0, w = W, du/dy = D1 U, dw/dy = D1 W
+  mfma_contract(a.D1T_e, RFo, KFe, T, CRP, CT, [&](int r, int cc, double v) {
+    if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
   });
+  mfma_contract(a.D1T_o, RFe, KFo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    if (r < Fe) S2[r * CRP + cc] = v;
+  });
+  __syncthreads();
+  for (int q = tid; q < Fe * NM; q += kNT) {
+    const int k = q / NM, el = q - k * NM, e = tile * ET + el;
+    if (e >= E) continue;
+    const bool pair = k < Fo;
+    for (int side = 0; side < (pair ? 2 : 1); ++side) {
+      const double sg = side == 0 ? 1.0 : -1.0;
+      const int j = side == 0 ? k : My - 1 - k;
+      const size_t off = 2 * ((size_t(j) * E + e) * K);
+      const double U = T[k * CRP + 2 * el] + (pair ? sg * T[(Fe + k) * CRP + 2 * el] : 0.0);
+      const double W = T[k * CRP + 2 * el + 1] + (pair ? sg * T[(Fe + k) * CRP + 2 * el + 1] : 0.0);
+      const double dU = S2[k * CRP + 2 * el] + (pair ? sg * S2[(Fe + k) * CRP + 2 * el] : 0.0);
+      const double dW = S2[k * CRP + 2 * el + 1] + (pair ? sg * S2[(Fe + k) * CRP + 2 * el + 1] : 0.0);
+      st_c(vel + off, U, 0.0);
+      st_c(vel + off + FS, 0.0, 0.0);
+      st_c(vel + off + 2 * FS, W, 0.0);
+      st_c(vel + off + 3 * FS, dU, 0.0);
+      st_c(vel + off + 4 * FS, dW, 0.0);
+    }
+  }
 }
 
 // LDS geometry of one workgroup; shared with the host launcher.
 void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR) {
   const int N = My - 2;
+  const int He = (N + 1) / 2, Ho = N / 2, Fe = He + 1, Fo = Ho + 1;
+  auto t4 = [](int n) { return 4 * ((n + 3) / 4); };
+  auto mx = [](int a, int b) { return a > b ? a : b; };
   *CRP = ((4 * ET + 15) / 16) * 16;
-  const int k2n = 4 * ((2 * N + 3) / 4);
-  const int km = 4 * ((My + 3) / 4);
-  int sr = k2n > My ? k2n : My;
-  // D1c reads T rows 1..4*KT(N); D1 reads rows 0..4*KT(My)-1
-  *SR = sr > km ? sr : km;
-  const int kn1 = 1 + 4 * ((N + 3) / 4);
-  *TR = km > kn1 ? km : kn1;
+  // S/S2: even solve reads rows < t4(2He), odd solve from 2He; D1 halves read
+  // rows < t4(Fe) and from Fe
+  int sr = mx(t4(2 * He), 2 * He + t4(2 * Ho));
+  sr = mx(sr, Fe + t4(Fo));
+  sr = mx(sr, mx(t4(Fe), My));
+  // T: D1int/D1 halves as above; D1c halves from row 1 and from row Fe + 1
+  int tr = mx(Fe + t4(Fo), t4(Fe));
+  tr = mx(tr, mx(1 + t4(He), Fe + 1 + t4(Ho)));
+  *SR = sr;
+  *TR = mx(tr, My);
 }
 
 int mode_member_tile(int My, int E) {

@@ -380,7 +380,7 @@ hipError_t launch_plane(int precision, int Nx, int Nz, const PlaneArgs& a, hipSt
       case 16: return run_plane<float, float, 8, 8, 24>(a, s);
       case 32: return run_plane<float, float, 16, 16, 16>(a, s);
       case 48: return run_plane<float, float, 24, 24, 12>(a, s);
-      case 64: return run_plane<float, float, 32, 32, 16>(a, s);
+      case 64: return run_plane<float, float, 32, 32, 32>(a, s);
     }
   }
   return hipErrorInvalidValue;

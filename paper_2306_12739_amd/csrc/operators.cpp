@@ -228,6 +228,21 @@ std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm) {
   return out;
 }
 
+std::vector<double> half_block(const double* M, int rows_out, int Cn, int ldm, bool even_in) {
+  const int ncol = even_in ? (Cn + 1) / 2 : Cn / 2;
+  std::vector<double> out(size_t(rows_out) * ncol, 0.0);
+  for (int i = 0; i < rows_out; ++i)
+    for (int k = 0; k < ncol; ++k) {
+      const double a = M[size_t(i) * ldm + k];
+      const double b = M[size_t(i) * ldm + (Cn - 1 - k)];
+      double v;
+      if (even_in) v = (k < Cn / 2) ? a + b : a;  // centre column when Cn is odd
+      else v = a - b;
+      out[size_t(i) * ncol + k] = v;
+    }
+  return out;
+}
+
 int build_operators(int My, int L, int P, double kxs, double kzs, double Re, double dt, double Ubot,
                     double Utop, HostOperators* out) {
   Cheb ch;

@@ -36,7 +36,10 @@ PREC_MIXED_FP32 = 1
 
 EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "dns_step",
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",
-            "dns_debug_stage0", "dns_kernel_times", "dns_host_operators"]
+            "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
+            "dns_create_grouped", "dns_group_handle"]
+
+MAX_GROUPS = 16
 
 
 class Geometry(ctypes.Structure):
@@ -47,6 +50,12 @@ class Geometry(ctypes.Structure):
 class StateView(ctypes.Structure):
     _fields_ = [("v_hat", ctypes.c_void_p), ("eta_hat", ctypes.c_void_p),
                 ("U00", ctypes.c_void_p), ("W00", ctypes.c_void_p), ("on_device", ctypes.c_int)]
+
+
+class Group(ctypes.Structure):
+    _fields_ = [("g", Geometry), ("Re", ctypes.c_double), ("Nx", ctypes.c_int),
+                ("Ny", ctypes.c_int), ("Nz", ctypes.c_int), ("members", ctypes.c_int),
+                ("dt", ctypes.c_double)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -89,6 +98,8 @@ def library(path=LIB_PATH):
     lib.dns_last_error.restype = ctypes.c_char_p
     lib.dns_debug_stage0.argtypes = [vp, _DP, _DP, _DP]
     lib.dns_kernel_times.argtypes = [vp, ctypes.c_int, _DP, _DP]
+    lib.dns_create_grouped.argtypes = [ctypes.POINTER(Group), ctypes.c_int, ctypes.POINTER(vp)]
+    lib.dns_group_handle.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
     lib.dns_host_operators.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        _DP, _DP, _DP, _DP, _DP, _DP, _DP]
@@ -129,10 +140,15 @@ def _ptr(a):
 class Ensemble:
     """One ensemble of flows sharing grid, box, Re and dt (include/dns.h)."""
 
-    def __init__(self, flow, Re, Lx, Lz, Nx, Ny, Nz, ensemble, dt, Uw=1.0, flux=0.0):
+    def __init__(self, flow, Re, Lx, Lz, Nx, Ny, Nz, ensemble, dt, Uw=1.0, flux=0.0,
+                 _borrowed=None):
         self.lib = library()
         self.flow, self.Re, self.Lx, self.Lz = flow, Re, Lx, Lz
         self.Nx, self.Ny, self.Nz, self.E, self.dt = Nx, Ny, Nz, ensemble, dt
+        self.owned = _borrowed is None
+        if not self.owned:  # a group's handle, owned by its GroupedEnsemble
+            self.h = _borrowed
+            return
         self.h = ctypes.c_void_p()
         g = Geometry(flow, Lx, Lz, Uw, flux)
         rc = self.lib.dns_create(ctypes.byref(g), Re, Nx, Ny, Nz, ensemble, dt, ctypes.byref(self.h))
@@ -146,9 +162,9 @@ class Ensemble:
         return rc
 
     def close(self):
-        if self.h:
+        if self.h and self.owned:
             self.lib.dns_destroy(self.h)
-            self.h = ctypes.c_void_p()
+        self.h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -250,3 +266,113 @@ class Ensemble:
             self.h, vel.view(np.float64).ctypes.data_as(_DP),
             nl.view(np.float64).ctypes.data_as(_DP), _ptr(means)))
         return vel, nl, means
+
+
+class GroupedEnsemble:
+    """Several ensembles (different Re, grid, box, dt) advanced by one step call
+    (dns_create_grouped).  ``groups``: list of dicts with keys flow, Re, Lx, Lz,
+    Nx, Ny, Nz, members, dt and optionally Uw, flux.  Members are numbered
+    group-major; ``self.groups[g]`` is group g's Ensemble (owned by this object)."""
+
+    def __init__(self, groups):
+        self.lib = library()
+        self.specs = [dict(g) for g in groups]
+        arr = (Group * len(groups))()
+        for i, g in enumerate(groups):
+            arr[i] = Group(Geometry(g["flow"], g["Lx"], g["Lz"], g.get("Uw", 1.0), g.get("flux", 0.0)),
+                           g["Re"], g["Nx"], g["Ny"], g["Nz"], g["members"], g["dt"])
+        self.h = ctypes.c_void_p()
+        rc = self.lib.dns_create_grouped(arr, len(groups), ctypes.byref(self.h))
+        if rc != DNS_OK:
+            raise DnsError(rc, self.lib.dns_last_error(None).decode())
+        self.base = list(np.cumsum([0] + [g["members"] for g in groups[:-1]]))
+        self.E = int(sum(g["members"] for g in groups))
+        self.groups = []
+        for i, g in enumerate(groups):
+            sub = ctypes.c_void_p()
+            self._check(self.lib.dns_group_handle(self.h, i, ctypes.byref(sub)))
+            self.groups.append(Ensemble(g["flow"], g["Re"], g["Lx"], g["Lz"], g["Nx"], g["Ny"],
+                                        g["Nz"], g["members"], g["dt"], _borrowed=sub))
+
+    def _check(self, rc):
+        if rc != DNS_OK:
+            raise DnsError(rc, self.lib.dns_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        for g in getattr(self, "groups", []):
+            g.h = ctypes.c_void_p()
+        if self.h:
+            self.lib.dns_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_option(self, key, value):
+        return self._check(self.lib.dns_set_option(self.h, key, int(value)))
+
+    def set_precision(self, prec):
+        return self.set_option(OPT_PRECISION, prec)
+
+    def set_stream(self, stream):
+        handle = getattr(stream, "cuda_stream", stream)
+        return self.set_option(OPT_STREAM, int(handle))
+
+    def set_state(self, v, eta, U, W, member0):
+        """State of members [member0, member0 + len(v)), inside one group, through
+        the grouped handle (global member numbers)."""
+        g = int(np.searchsorted(self.base, member0, side="right") - 1)
+        ens = self.groups[g]
+        v = np.ascontiguousarray(v, dtype=np.complex128)
+        eta = np.ascontiguousarray(eta, dtype=np.complex128)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        if v.shape[1:] != ens.shape_spec or U.shape != (v.shape[0], ens.Ny):
+            raise ValueError("state arrays do not match the group's grid")
+        sv = StateView(v.ctypes.data, eta.ctypes.data, U.ctypes.data, W.ctypes.data, 0)
+        return self._check(self.lib.dns_set_state(self.h, member0, v.shape[0], ctypes.byref(sv)))
+
+    def get_state(self, member0, count):
+        g = int(np.searchsorted(self.base, member0, side="right") - 1)
+        ens = self.groups[g]
+        v = np.zeros((count,) + ens.shape_spec, dtype=np.complex128)
+        eta = np.zeros_like(v)
+        U = np.zeros((count, ens.Ny))
+        W = np.zeros_like(U)
+        sv = StateView(v.ctypes.data, eta.ctypes.data, U.ctypes.data, W.ctypes.data, 0)
+        self._check(self.lib.dns_get_state(self.h, member0, count, ctypes.byref(sv)))
+        return v, eta, U, W
+
+    def step(self, nsteps=1):
+        return self._check(self.lib.dns_step(self.h, int(nsteps)))
+
+    def sync(self):
+        return self._check(self.lib.dns_sync(self.h))
+
+    def stats_reset(self):
+        return self._check(self.lib.dns_stats_reset(self.h))
+
+    def stats(self, allow_nonfinite=False):
+        """Per-member diagnostics over all groups (group-major)."""
+        E = self.E
+        out = {k: np.zeros(E) for k in ("energy", "dissipation", "power", "flux", "gamma",
+                                         "div_max", "tau_lower", "tau_upper")}
+        out["failed"] = np.zeros(E, dtype=np.int32)
+        so = StatsOut()
+        for k, arr in out.items():
+            setattr(so, k, arr.ctypes.data_as(_IP if k == "failed" else _DP))
+        rc = self.lib.dns_stats(self.h, ctypes.byref(so))
+        if rc != DNS_OK and not (allow_nonfinite and rc == DNS_E_NONFINITE):
+            self._check(rc)
+        out["samples"], out["steps"], out["rc"] = so.samples, so.steps, rc
+        return out

@@ -112,6 +112,30 @@ WORKLOADS = {
 }
 
 
+# Uneven batched ensemble: three Couette groups of different Re and grid in one
+# step call (members 64 / 40 / 24, 500 steps each); per-group seeds 1003 + g.
+GROUPED_WORKLOADS = {
+    "couette-grouped-re400-600-1000-e128": dict(
+        steps=500,
+        groups=[
+            dict(flow=0, Re=400.0, Lx=1.75 * np.pi, Lz=1.2 * np.pi, Nx=16, Ny=33, Nz=16,
+                 members=64, dt=0.02, amplitude=0.2, spectrum="k2", seed=1003),
+            dict(flow=0, Re=600.0, Lx=1.75 * np.pi, Lz=1.2 * np.pi, Nx=32, Ny=49, Nz=32,
+                 members=40, dt=0.02, amplitude=0.2, spectrum="k2", seed=1004),
+            dict(flow=0, Re=1000.0, Lx=1.75 * np.pi, Lz=1.2 * np.pi, Nx=48, Ny=65, Nz=48,
+                 members=24, dt=0.02, amplitude=0.2, spectrum="k2", seed=1005),
+        ]),
+}
+
+
+def group_state(group, members=None, seed=None):
+    """Initial state of one group of a grouped workload."""
+    g = group
+    return random_state(g["flow"], g["Lx"], g["Lz"], g["Nx"], g["Ny"], g["Nz"],
+                        g["members"] if members is None else members, g["amplitude"],
+                        g["seed"] if seed is None else seed, spectrum=g["spectrum"])
+
+
 def workload_state(name, ensemble=None, seed=None):
     w = WORKLOADS[name]
     return random_state(w["flow"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"],

@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2306_12739_amd import dns
@@ -56,3 +58,25 @@ def test_null_handle_calls_are_rejected():
     assert lib.dns_stats(None, None) == dns.DNS_E_STATE
     assert lib.dns_set_option(None, dns.OPT_PRECISION, 0) == dns.DNS_E_STATE
     lib.dns_destroy(None)   # NULL-safe
+
+
+def test_grouped_arguments_rejected_without_gpu():
+    lib = dns.library()
+    h = ctypes.c_void_p()
+    assert lib.dns_create_grouped(None, 1, ctypes.byref(h)) == dns.DNS_E_INVALID
+    geo = dns.Geometry(0, 1.75 * np.pi, 1.2 * np.pi, 1.0, 0.0)
+    arr = (dns.Group * (dns.MAX_GROUPS + 1))()
+    for i in range(dns.MAX_GROUPS + 1):
+        arr[i] = dns.Group(geo, 400.0, 16, 33, 16, 2, 0.02)
+    assert lib.dns_create_grouped(arr, 0, ctypes.byref(h)) == dns.DNS_E_INVALID
+    assert lib.dns_create_grouped(arr, dns.MAX_GROUPS + 1, ctypes.byref(h)) == dns.DNS_E_INVALID
+    # a bad group is named in the message, before any device allocation
+    bad = (dns.Group * 2)()
+    bad[0] = dns.Group(geo, 400.0, 16, 33, 16, 2, 0.02)
+    bad[1] = dns.Group(geo, 400.0, 16, 3, 16, 2, 0.02)
+    bad_first = (dns.Group * 1)(bad[1])
+    assert lib.dns_create_grouped(bad_first, 1, ctypes.byref(h)) == dns.DNS_E_INVALID
+    assert b"group 0" in lib.dns_last_error(None)
+    assert not h.value
+    sub = ctypes.c_void_p()
+    assert lib.dns_group_handle(None, 0, ctypes.byref(sub)) == dns.DNS_E_STATE
