@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--ensemble", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tile shapes instead of running the tuner first")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
@@ -149,6 +151,7 @@ def main():
     ens.set_precision(dns.PREC_FP64 if args.precision == "fp64" else dns.PREC_MIXED_FP32)
     ens.set_option(dns.OPT_GRAPH, 0 if args.no_graph else 1)
     ens.set_state(*inputs.workload_state(name, ensemble=E))
+    tuning = None if args.no_tune else ens.tune()
 
     ens.step(args.warmup)
     torch.cuda.synchronize()
@@ -219,6 +222,7 @@ def main():
         "grid_point_steps_per_s_nominal": value * w["Nx"] * w["Ny"] * w["Nz"],
         "wall_s": wall,
         "kernels": per_kernel,
+        "tuning": tuning,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -108,6 +108,11 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
 #define DNS_OPT_STREAM 2      /* value: hipStream_t cast to integer (0 = default) */
 #define DNS_OPT_GRAPH 3       /* value: 1 capture one step as a hipGraph, 0 eager */
 #define DNS_OPT_STATS 4       /* value: 1 accumulate one-point statistics each step */
+#define DNS_OPT_PLANE_ROWS 5  /* value: physical z rows per chunk of the advection
+                                 kernel, one of the built variants (DNS_E_UNSUPPORTED
+                                 otherwise); applies to the current precision   */
+#define DNS_OPT_MODE_TILE 6   /* value: members per workgroup of the per-mode kernel,
+                                 1, 2, 4 or 8, fitting 160 KB of LDS           */
 
 #define DNS_PREC_FP64 0        /* every stage in FP64                               */
 #define DNS_PREC_MIXED_FP32 1  /* y-derivative products and x-z FFTs in FP32, FP32
@@ -200,6 +205,28 @@ void dns_destroy(dns_handle* h);
 
 /* Message of the last error on h (or of the calling thread when h is NULL). */
 const char* dns_last_error(const dns_handle* h);
+
+/* Tile-shape tuner.  Times every built chunk-row variant of the advection
+ * kernel and every admissible member tile of the per-mode kernel on the current
+ * state (HIP events on the handle's stream, 5 launches each, the per-mode
+ * kernel at its second sub-step; the state does not advance) and keeps the
+ * fastest of each for the current precision.  Tile shapes change the order of
+ * floating-point operations in the FFTs, never the method.
+ *   cache_path : optional text file (NULL: none).  A line "<precision> <Nx>
+ *                <Ny> <Nz> <members> <plane_rows> <mode_members> <plane_ms>
+ *                <mode_ms>" with this handle's key is applied without timing
+ *                (the last such line wins); new results are appended.
+ *   out        : NULL, or one dns_tuning per group (1 for a plain handle).
+ * Synchronises.  Errors: DNS_E_HIP, DNS_E_INVALID (cache not writable or its
+ * entry not applicable). */
+typedef struct {
+  int plane_rows;     /* chosen chunk rows of the advection kernel   */
+  int mode_members;   /* chosen members per per-mode workgroup       */
+  double plane_ms;    /* its time per launch (from the cache if so)  */
+  double mode_ms;
+  int from_cache;     /* 1 if read from cache_path                   */
+} dns_tuning;
+int dns_tune(dns_handle* h, const char* cache_path, dns_tuning* out);
 
 /* Stage intermediates for verification (not needed for time stepping).
  * From the current state, without advancing it, computes the first RK3

@@ -29,7 +29,7 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    flags = COMMON + (DEVICE if src.endswith(".hip") else [])
+    flags = COMMON + DEVICE
     cmd = [HIPCC] + flags + ["-c", path, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:

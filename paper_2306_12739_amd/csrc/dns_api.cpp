@@ -58,6 +58,7 @@ struct dns_handle {
   double* staging = nullptr;
   size_t staging_bytes = 0;
   int ET = 1, ntiles = 1;
+  int plane_var[2] = {0, 0};  // plane-kernel variant per precision (FP64, mixed)
   // progress
   long long steps = 0, samples = 0;
   bool vel_fresh = false;
@@ -208,6 +209,27 @@ PlaneArgs plane_args(dns_handle* h, bool sums) {
   return a;
 }
 
+hipError_t plane_launch(dns_handle* h, bool sums) {
+  return launch_plane(h->precision, h->Nx, h->Nz, h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1],
+                      plane_args(h, sums), h->stream);
+}
+
+// Members per mode-kernel workgroup: 1, 2, 4 or 8, at most the ensemble size
+// (rounded up to a power of two) and within 160 KB of LDS.
+bool mode_tile_ok(const dns_handle* h, int et) {
+  if (et != 1 && et != 2 && et != 4 && et != 8) return false;
+  if (et > 1 && et / 2 >= h->E) return false;
+  int crp, sr, tr;
+  mode_lds_geometry(h->My, et, &crp, &sr, &tr);
+  return size_t(2 * sr + tr) * crp * sizeof(double) <= 160 * 1024;
+}
+
+void set_mode_tile(dns_handle* h, int et) {
+  h->ET = et;
+  h->ntiles = (h->E + et - 1) / et;
+  mode_lds_geometry(h->My, et, &h->CRP, &h->SR, &h->TR);
+}
+
 StatsArgs stats_args(dns_handle* h) {
   StatsArgs a{};
   a.psum = h->psum;
@@ -239,7 +261,7 @@ int refresh_velocities(dns_handle* h) {
 // Enqueue one time step; requires the velocity buffer to hold the state's velocities.
 int enqueue_step(dns_handle* h) {
   for (int s = 0; s < 3; ++s) {
-    HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, s == 0), h->stream));
+    HIP_OR_FAIL(h, plane_launch(h, s == 0));
     if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h), h->stats_on ? 1 : 0, h->stream));
     HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s), h->stream));
   }
@@ -396,9 +418,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     h->Ubot = -h->Uw;
     h->Utop = h->Uw;
   }
-  h->ET = mode_member_tile(h->My, h->E);
-  h->ntiles = (h->E + h->ET - 1) / h->ET;
-  mode_lds_geometry(h->My, h->ET, &h->CRP, &h->SR, &h->TR);
+  set_mode_tile(h, mode_member_tile(h->My, h->E));
 
   HostOperators ho;
   if (build_operators(h->My, h->L, h->P, h->kxs, h->kzs, Re, dt, h->Ubot, h->Utop, &ho) != 0) {
@@ -650,6 +670,25 @@ int dns_set_option(dns_handle* h, int key, long long value) {
       h->stats_on = value != 0;
       invalidate_graph(h);
       return DNS_OK;
+    case DNS_OPT_PLANE_ROWS: {
+      if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
+      int rows[3];
+      const int n = plane_variants(h->precision, h->Nx, rows);
+      for (int v = 0; v < n; ++v)
+        if (rows[v] == value) {
+          h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1] = v;
+          invalidate_graph(h);
+          return DNS_OK;
+        }
+      return fail(h, DNS_E_UNSUPPORTED, "no plane-kernel variant with that many chunk rows");
+    }
+    case DNS_OPT_MODE_TILE:
+      if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
+      if (!mode_tile_ok(h, int(value)))
+        return fail(h, DNS_E_INVALID, "mode tile must be 1, 2, 4 or 8 members and fit in LDS");
+      set_mode_tile(h, int(value));
+      invalidate_graph(h);
+      return DNS_OK;
   }
   return fail(h, DNS_E_INVALID, "unknown option key");
 }
@@ -837,7 +876,7 @@ int dns_stats(dns_handle* h, dns_stats_out* o) {
   HIP_OR_FAIL(h, hipMemsetAsync(h->divmax, 0, sizeof(unsigned long long) * h->E, h->stream));
   int rc = refresh_velocities(h);
   if (rc) return rc;
-  HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, true), h->stream));
+  HIP_OR_FAIL(h, plane_launch(h, true));
   HIP_OR_FAIL(h, launch_stats(stats_args(h), 0, h->stream));
   const int E = h->E, My = h->My;
   std::vector<double> inst(size_t(NDI) * E), gam(E), acc(size_t(NPA) * My * E + 2 * E);
@@ -934,7 +973,7 @@ int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
   if (h->grouped()) return fail(h, DNS_E_INVALID, "call this on a group's handle (dns_group_handle)");
   int rc = refresh_velocities(h);
   if (rc) return rc;
-  HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
+  HIP_OR_FAIL(h, plane_launch(h, false));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   const int E = h->E, My = h->My, K = h->K;
   const size_t vt = vt_size(h->precision);
@@ -966,6 +1005,138 @@ int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
   return DNS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Average device time of nreps launches (after one untimed launch), HIP events.
+template <class Launch>
+int time_launches(dns_handle* h, int nreps, Launch launch, double* ms) {
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(h, hipEventCreate(&e0));
+  HIP_OR_FAIL(h, hipEventCreate(&e1));
+  hipError_t err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e0, h->stream);
+  for (int r = 0; r < nreps && err == hipSuccess; ++r) err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e1, h->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(h, DNS_E_HIP, std::string("timing launches: ") + hipGetErrorString(err));
+  *ms = double(t) / nreps;
+  return DNS_OK;
+}
+
+std::string tune_key(const dns_handle* h) {
+  return std::to_string(h->precision) + " " + std::to_string(h->Nx) + " " + std::to_string(h->Ny) + " " +
+         std::to_string(h->Nz) + " " + std::to_string(h->E);
+}
+
+// Last cache line "<precision> <Nx> <Ny> <Nz> <E> <plane_rows> <mode_members> <plane_ms> <mode_ms>"
+// whose key matches h.
+bool cache_lookup(const dns_handle* h, const char* path, dns_tuning* t) {
+  if (!path) return false;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  int p, nx, ny, nz, e, rows, mem;
+  double pm, mm;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %lf %lf", &p, &nx, &ny, &nz, &e, &rows, &mem, &pm, &mm) != 9)
+      continue;
+    if (p == h->precision && nx == h->Nx && ny == h->Ny && nz == h->Nz && e == h->E) {
+      t->plane_rows = rows;
+      t->mode_members = mem;
+      t->plane_ms = pm;
+      t->mode_ms = mm;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
+  dns_tuning t{};
+  if (cache_lookup(h, cache, &t)) {
+    int rc = dns_set_option(h, DNS_OPT_PLANE_ROWS, t.plane_rows);
+    if (rc == DNS_OK) rc = dns_set_option(h, DNS_OPT_MODE_TILE, t.mode_members);
+    if (rc != DNS_OK) return fail(h, rc, "tune cache entry does not apply: " + h->err);
+    t.from_cache = 1;
+    if (out) *out = t;
+    return DNS_OK;
+  }
+  constexpr int kReps = 5;
+  if (!h->vel_fresh) {
+    const int rc = refresh_velocities(h);
+    if (rc) return rc;
+  }
+  const int pi = h->precision == DNS_PREC_FP64 ? 0 : 1;
+  int rows[3];
+  const int nv = plane_variants(h->precision, h->Nx, rows);
+  int best_v = 0;
+  double best_p = 1e30;
+  for (int v = 0; v < nv; ++v) {
+    h->plane_var[pi] = v;
+    double ms;
+    const int rc = time_launches(h, kReps, [&] { return plane_launch(h, false); }, &ms);
+    if (rc) return rc;
+    if (ms < best_p) best_p = ms, best_v = v;
+  }
+  h->plane_var[pi] = best_v;
+  // the mode kernel's second sub-step on the current stage buffers (the next
+  // step rewrites its history first)
+  int best_et = h->ET;
+  double best_m = 1e30;
+  for (int et = 1; et <= 8; et *= 2) {
+    if (!mode_tile_ok(h, et)) continue;
+    set_mode_tile(h, et);
+    double ms;
+    const int rc = time_launches(h, kReps, [&] { return launch_mode(h->precision, mode_args(h, 1), h->stream); }, &ms);
+    if (rc) return rc;
+    if (ms < best_m) best_m = ms, best_et = et;
+  }
+  set_mode_tile(h, best_et);
+  h->vel_fresh = false;
+  invalidate_graph(h);
+  t.plane_rows = rows[best_v];
+  t.mode_members = best_et;
+  t.plane_ms = best_p;
+  t.mode_ms = best_m;
+  t.from_cache = 0;
+  if (cache) {
+    std::FILE* f = std::fopen(cache, "a");
+    if (!f) return fail(h, DNS_E_INVALID, std::string("cannot append to tune cache ") + cache);
+    std::fprintf(f, "%s %d %d %.6f %.6f\n", tune_key(h).c_str(), t.plane_rows, t.mode_members, t.plane_ms,
+                 t.mode_ms);
+    std::fclose(f);
+  }
+  if (out) *out = t;
+  return DNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dns_tune(dns_handle* h, const char* cache_path, dns_tuning* out) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    for (size_t g = 0; g < h->sub.size(); ++g) {
+      const int rc = tune_one(h->sub[g], cache_path, out ? out + g : nullptr);
+      if (rc) return fail(h, rc, "group " + std::to_string(g) + ": " + h->sub[g]->err);
+    }
+    invalidate_graph(h);
+    return DNS_OK;
+  }
+  return tune_one(h, cache_path, out);
+}
+
 int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
   ORDER_AFTER_PARENT(h);
@@ -980,11 +1151,11 @@ int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms
   HIP_OR_FAIL(h, hipEventCreate(&e1));
   HIP_OR_FAIL(h, hipEventCreate(&e2));
   // one untimed launch of each, then nreps timed launches of each
-  HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
+  HIP_OR_FAIL(h, plane_launch(h, false));
   HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, 1), h->stream));
   HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
   for (int r = 0; r < nreps; ++r)
-    HIP_OR_FAIL(h, launch_plane(h->precision, h->Nx, h->Nz, plane_args(h, false), h->stream));
+    HIP_OR_FAIL(h, plane_launch(h, false));
   HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
   for (int r = 0; r < nreps; ++r) HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, 1), h->stream));
   HIP_OR_FAIL(h, hipEventRecord(e2, h->stream));

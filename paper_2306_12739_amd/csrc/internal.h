@@ -78,7 +78,10 @@ struct ModeArgs {
 };
 
 // Kernel launchers (kernels_*.hip).  Return hipSuccess or the launch error.
-hipError_t launch_plane(int precision, int Nx, int Nz, const PlaneArgs& a, hipStream_t s);
+hipError_t launch_plane(int precision, int Nx, int Nz, int variant, const PlaneArgs& a, hipStream_t s);
+// Chunk-row counts of the plane-kernel variants built for (precision, Nx);
+// returns how many (<= 3), index 0 being the default.
+int plane_variants(int precision, int Nx, int* rows);
 bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
 int mode_member_tile(int My, int E);

@@ -66,6 +66,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 constexpr int kNT = 512;
 
+enum Phys { PU = 0, PV, PW, PNU, PNV, PNW, PVY, NPHYS };
+
 template <typename T, int L, int P, int PP>
 struct PlaneCfg {
   static constexpr int MX = 3 * L, MZ = 3 * P, NZ = 2 * P - 1;
@@ -79,10 +81,11 @@ struct PlaneCfg {
   static constexpr int MID = MIDZ > MIDX ? MIDZ : MIDX;
   static constexpr int NPT = PP * MX;                          // physical points per chunk
   static constexpr int NACC = (3 * L * NZ + kNT - 1) / kNT;
+  // static LDS of plane_kernel: roots, zb, mid, phys and the reduction scratch
+  static constexpr size_t kLdsBytes =
+      (MX + MZ + PP + ZB + MID) * 2 * sizeof(T) + NPHYS * NPT * sizeof(T) + 8 * (kNT / 64) * sizeof(double);
   static_assert(MZ % PP == 0 && PP % 2 == 0, "chunk rows must divide Mz and pair up");
 };
-
-enum Phys { PU = 0, PV, PW, PNU, PNV, PNW, PVY, NPHYS };
 
 }  // namespace
 
@@ -365,22 +368,67 @@ bool plane_supported(int Nx, int Nz) {
   return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64);
 }
 
-// precision 0: FP64 storage and arithmetic; 1/2: FP32 storage and FFT arithmetic.
-hipError_t launch_plane(int precision, int Nx, int Nz, const PlaneArgs& a, hipStream_t s) {
+// Chunk-row variants (PP) built for each precision and grid; index 0 is the
+// default, the others are candidates for the tuner.  Every variant keeps the
+// workgroup's LDS within 160 KB.
+namespace {
+constexpr int kVar64[4][3] = {{24, 12, 8}, {16, 24, 8}, {12, 8, 0}, {16, 12, 8}};
+constexpr int kVar32[4][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 16}};
+int grid_index(int Nx) { return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : -1; }
+
+template <typename T, int L, int PP>
+hipError_t run_if_fits(const PlaneArgs& a, hipStream_t s) {
+  if constexpr ((3 * L) % PP == 0) {
+    if constexpr (PlaneCfg<T, L, L, PP>::kLdsBytes <= 160 * 1024) return run_plane<T, T, L, L, PP>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int L>
+hipError_t run_rows(int pp, const PlaneArgs& a, hipStream_t s) {
+  switch (pp) {
+    case 8: return run_if_fits<T, L, 8>(a, s);
+    case 12: return run_if_fits<T, L, 12>(a, s);
+    case 16: return run_if_fits<T, L, 16>(a, s);
+    case 24: return run_if_fits<T, L, 24>(a, s);
+    case 32: return run_if_fits<T, L, 32>(a, s);
+    case 36: return run_if_fits<T, L, 36>(a, s);
+    case 48: return run_if_fits<T, L, 48>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+int plane_variants(int precision, int Nx, int* rows) {
+  const int gi = grid_index(Nx);
+  if (gi < 0) return 0;
+  const int(*tab)[3] = precision == 0 ? kVar64 : kVar32;
+  int n = 0;
+  for (int v = 0; v < 3; ++v)
+    if (tab[gi][v]) rows[n++] = tab[gi][v];
+  return n;
+}
+
+// precision 0: FP64 storage and arithmetic; 1: FP32 storage and FFT arithmetic.
+hipError_t launch_plane(int precision, int Nx, int Nz, int variant, const PlaneArgs& a, hipStream_t s) {
   if (!plane_supported(Nx, Nz)) return hipErrorInvalidValue;
+  int rows[3];
+  const int n = plane_variants(precision, Nx, rows);
+  if (variant < 0 || variant >= n) return hipErrorInvalidValue;
+  const int pp = rows[variant];
   if (precision == 0) {
     switch (Nx) {
-      case 16: return run_plane<double, double, 8, 8, 24>(a, s);
-      case 32: return run_plane<double, double, 16, 16, 16>(a, s);
-      case 48: return run_plane<double, double, 24, 24, 12>(a, s);
-      case 64: return run_plane<double, double, 32, 32, 16>(a, s);
+      case 16: return run_rows<double, 8>(pp, a, s);
+      case 32: return run_rows<double, 16>(pp, a, s);
+      case 48: return run_rows<double, 24>(pp, a, s);
+      case 64: return run_rows<double, 32>(pp, a, s);
     }
   } else {
     switch (Nx) {
-      case 16: return run_plane<float, float, 8, 8, 24>(a, s);
-      case 32: return run_plane<float, float, 16, 16, 16>(a, s);
-      case 48: return run_plane<float, float, 24, 24, 12>(a, s);
-      case 64: return run_plane<float, float, 32, 32, 32>(a, s);
+      case 16: return run_rows<float, 8>(pp, a, s);
+      case 32: return run_rows<float, 16>(pp, a, s);
+      case 48: return run_rows<float, 24>(pp, a, s);
+      case 64: return run_rows<float, 32>(pp, a, s);
     }
   }
   return hipErrorInvalidValue;

@@ -30,6 +30,8 @@ OPT_PRECISION = 1
 OPT_STREAM = 2
 OPT_GRAPH = 3
 OPT_STATS = 4
+OPT_PLANE_ROWS = 5
+OPT_MODE_TILE = 6
 
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1
@@ -37,7 +39,7 @@ PREC_MIXED_FP32 = 1
 EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "dns_step",
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",
             "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
-            "dns_create_grouped", "dns_group_handle"]
+            "dns_create_grouped", "dns_group_handle", "dns_tune"]
 
 MAX_GROUPS = 16
 
@@ -56,6 +58,17 @@ class Group(ctypes.Structure):
     _fields_ = [("g", Geometry), ("Re", ctypes.c_double), ("Nx", ctypes.c_int),
                 ("Ny", ctypes.c_int), ("Nz", ctypes.c_int), ("members", ctypes.c_int),
                 ("dt", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("plane_rows", ctypes.c_int), ("mode_members", ctypes.c_int),
+                ("plane_ms", ctypes.c_double), ("mode_ms", ctypes.c_double),
+                ("from_cache", ctypes.c_int)]
+
+
+def _tuning_dict(t):
+    return {"plane_rows": t.plane_rows, "mode_members": t.mode_members, "plane_ms": t.plane_ms,
+            "mode_ms": t.mode_ms, "from_cache": bool(t.from_cache)}
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -100,6 +113,7 @@ def library(path=LIB_PATH):
     lib.dns_kernel_times.argtypes = [vp, ctypes.c_int, _DP, _DP]
     lib.dns_create_grouped.argtypes = [ctypes.POINTER(Group), ctypes.c_int, ctypes.POINTER(vp)]
     lib.dns_group_handle.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.dns_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     lib.dns_host_operators.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        _DP, _DP, _DP, _DP, _DP, _DP, _DP]
@@ -250,6 +264,13 @@ class Ensemble:
         out["rc"] = rc
         return out
 
+    def tune(self, cache_path=None):
+        """Pick the fastest plane chunk rows and mode member tile (dns_tune)."""
+        t = Tuning()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.lib.dns_tune(self.h, path, ctypes.byref(t)))
+        return _tuning_dict(t)
+
     def kernel_times(self, nreps=10):
         """(plane_ms, mode_ms): average device time per launch, HIP events."""
         p = ctypes.c_double()
@@ -361,6 +382,13 @@ class GroupedEnsemble:
 
     def stats_reset(self):
         return self._check(self.lib.dns_stats_reset(self.h))
+
+    def tune(self, cache_path=None):
+        """Tune every group; one dict per group."""
+        arr = (Tuning * len(self.groups))()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(self.lib.dns_tune(self.h, path, arr))
+        return [_tuning_dict(t) for t in arr]
 
     def stats(self, allow_nonfinite=False):
         """Per-member diagnostics over all groups (group-major)."""
