@@ -18,6 +18,9 @@ ensemble DNS") step by step, in the paper's order and notation:
 * ``step``        -- one CN/RK3 time step of the whole ensemble (Sec. 3.1).
 * ``diagnostics`` -- energy, dissipation, power input, flux, one-point
                      statistics (Sec. 4, one-point statistics paragraph).
+* ``sno``         -- learned spin-up (not in the paper): channel form of a
+                     state and back to an admissible state, a spectral neural
+                     operator with its gradient, AdamW.
 
 Every function here is written for clarity, not speed: library primitives
 (numpy FFTs, ``numpy.linalg.solve``, matrix products) are the only building
@@ -30,9 +33,10 @@ from .spectral import SpectralGrid
 from .operators import ModeOperators, MeanOperators
 from .step import OracleDNS
 from . import diagnostics
+from . import sno
 
 __all__ = [
     "nodes", "diff_matrix", "dirichlet_d2", "clamped_matrices",
     "clenshaw_curtis_weights", "SpectralGrid", "ModeOperators",
-    "MeanOperators", "OracleDNS", "diagnostics",
+    "MeanOperators", "OracleDNS", "diagnostics", "sno",
 ]
