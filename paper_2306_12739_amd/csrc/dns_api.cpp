@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/dns.h"
+#include "../../include/sno.h"
 #include "internal.h"
 
 using namespace dns;
@@ -51,6 +52,7 @@ struct dns_handle {
   int CRP = 16, SR = 0, TR = 0;
   double *lift_h[2] = {nullptr, nullptr}, *green_h[2] = {nullptr, nullptr};
   double *ccw_h = nullptr, *D1 = nullptr, *ccw = nullptr;
+  double *cheb_cinv = nullptr, *cheb_t = nullptr;  // channel form: coefficients <-> node values
   double* gamma = nullptr;
   int* failed = nullptr;
   unsigned long long* divmax = nullptr;
@@ -124,7 +126,7 @@ void free_all(dns_handle* h) {
                   h->means, h->psum, h->opsT[0], h->opsT[1], h->meanT[0], h->meanT[1],
                   h->D1intT_e, h->D1intT_o, h->D1cT_e, h->D1cT_o, h->D1T_e, h->D1T_o,
                   h->lift_h[0], h->lift_h[1], h->green_h[0], h->green_h[1], h->ccw_h,
-                  h->D1, h->ccw,
+                  h->D1, h->ccw, h->cheb_cinv, h->cheb_t,
                   h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging};
   for (void* p : bufs)
     if (p) hipFree(p);
@@ -1135,6 +1137,87 @@ int dns_tune(dns_handle* h, const char* cache_path, dns_tuning* out) {
     return DNS_OK;
   }
   return tune_one(h, cache_path, out);
+}
+
+namespace {
+
+// Chebyshev interpolation on the ascending nodes y_j = -cos(pi j / n), n = My - 1:
+// T_k(y_j) = (-1)^k cos(pi k j / n); coefficients by the discrete cosine
+// (DCT-I) orthogonality, a_k = 2 / (n c_k) sum_j T_k(y_j) f_j / c_j, c_0 = c_n = 2.
+int ensure_cheb(dns_handle* h) {
+  if (h->cheb_cinv) return DNS_OK;
+  const int My = h->My, n = My - 1;
+  std::vector<double> T(size_t(My) * My), Ci(size_t(My) * My);
+  auto Tk = [&](int k, int j) {
+    const long long r = (long long)k * j % (2 * n);
+    return ((k & 1) ? -1.0 : 1.0) * std::cos(M_PI * double(r) / n);
+  };
+  for (int j = 0; j < My; ++j)
+    for (int k = 0; k < My; ++k) T[size_t(j) * My + k] = Tk(k, j);
+  for (int k = 0; k < My; ++k)
+    for (int j = 0; j < My; ++j) {
+      const double ck = (k == 0 || k == n) ? 2.0 : 1.0, cj = (j == 0 || j == n) ? 2.0 : 1.0;
+      Ci[size_t(k) * My + j] = 2.0 / (n * ck) * Tk(k, j) / cj;
+    }
+  if (dalloc(&h->cheb_cinv, Ci.size()) != hipSuccess || dalloc(&h->cheb_t, T.size()) != hipSuccess)
+    return fail(h, DNS_E_NOMEM, "hipMalloc Chebyshev matrices");
+  HIP_OR_FAIL(h, hipMemcpy(h->cheb_cinv, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(h, hipMemcpy(h->cheb_t, T.data(), T.size() * 8, hipMemcpyHostToDevice));
+  return DNS_OK;
+}
+
+}  // namespace
+
+int dns_get_channels(dns_handle* h, int member0, int count, float* out) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    dns_handle* sh;
+    int m0;
+    const int rc = route(h, member0, count, &sh, &m0);
+    return rc ? rc : forward(h, sh, dns_get_channels(sh, m0, count, out));
+  }
+  if (!out) return fail(h, DNS_E_INVALID, "out is NULL");
+  if (member0 < 0 || count < 1 || member0 + count > h->E) return fail(h, DNS_E_INVALID, "member range out of bounds");
+  int rc = ensure_cheb(h);
+  if (rc) return rc;
+  const int Mx = 3 * h->Nx / 2, Mz = 3 * h->Nz / 2;
+  rc = ensure_staging(h, size_t(count) * 3 * h->My * Mx * Mz * sizeof(double));
+  if (rc) return rc;
+  rc = refresh_velocities(h);
+  if (rc) return rc;
+  HIP_OR_FAIL(h, launch_to_channels(h->precision, h->vel, h->staging, h->cheb_cinv, out, h->My, h->E, h->K, h->L,
+                                    h->NZ, Mx, Mz, member0, count, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  return DNS_OK;
+}
+
+int dns_set_channels(dns_handle* h, int member0, int count, const float* in) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    dns_handle* sh;
+    int m0;
+    const int rc = route(h, member0, count, &sh, &m0);
+    return rc ? rc : forward(h, sh, dns_set_channels(sh, m0, count, in));
+  }
+  if (!in) return fail(h, DNS_E_INVALID, "in is NULL");
+  if (member0 < 0 || count < 1 || member0 + count > h->E) return fail(h, DNS_E_INVALID, "member range out of bounds");
+  int rc = ensure_cheb(h);
+  if (rc) return rc;
+  const int Mx = 3 * h->Nx / 2, Mz = 3 * h->Nz / 2;
+  const size_t nphys = size_t(count) * 3 * h->My * Mx * Mz;
+  const size_t nspec = size_t(count) * 3 * h->My * h->K * 2;
+  rc = ensure_staging(h, (nphys + nspec) * sizeof(double));
+  if (rc) return rc;
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  HIP_OR_FAIL(h, launch_from_channels(in, h->staging, h->staging + nphys, h->cheb_t, h->v, h->eta, h->U, h->W, h->My,
+                                      h->E, h->L, h->NZ, Mx, Mz, member0, count, h->kxs, h->kzs, h->Ubot, h->Utop,
+                                      h->stream));
+  HIP_OR_FAIL(h, hipMemsetAsync(h->failed + member0, 0, sizeof(int) * count, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  h->vel_fresh = false;
+  return DNS_OK;
 }
 
 int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms) {

@@ -142,4 +142,41 @@ struct HostOperators {
 int build_operators(int My, int L, int P, double kxs, double kzs, double Re, double dt,
                     double Ubot, double Utop, HostOperators* out);
 
+// ---- channel form of states (learned spin-up) -------------------------------------
+// cinv: Chebyshev coefficients from node values (My x My); tmat: node values
+// from coefficients (My x My); phys: count * 3 * My planes of Mz x Mx doubles;
+// spec: count * 3 * My * K complex doubles.
+hipError_t launch_to_channels(int precision, const void* vel, double* phys, const double* cinv, float* out, int My,
+                              int E, int K, int L, int NZ, int Mx, int Mz, int member0, int count, hipStream_t s);
+hipError_t launch_from_channels(const float* in, double* phys, double* spec, const double* tmat, double* v,
+                                double* eta, double* U, double* W, int My, int E, int L, int NZ, int Mx, int Mz,
+                                int member0, int count, double kxs, double kzs, double Ubot, double Utop,
+                                hipStream_t s);
+
+// ---- spectral neural operator (learned spin-up) --------------------------------
+// C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * C[b][m][n]; element
+// (m, k) of batch b of A sits at A + b * sab + m * sam + k * sak (likewise B, C).
+// reduce_batch: C has no batch index and receives the sum over all batches.
+// beta == 0 never reads C.
+struct GemmArgs {
+  const float* A;
+  long long sam, sak, sab;
+  const float* B;
+  long long sbk, sbn, sbb;
+  float* C;
+  long long scm, scn, scb;
+  int M, N, K, batch;
+  float alpha, beta;
+  int reduce_batch;
+};
+hipError_t launch_gemm(const GemmArgs& g, bool bf16, hipStream_t s);
+hipError_t launch_bias_act(float* x, float* h, const float* bias, int B, int C, int P, hipStream_t s);
+hipError_t launch_gelu_bwd(float* dh, const float* z, long long n, hipStream_t s);
+hipError_t launch_channel_sum(const float* x, float* out, int B, int C, int P, hipStream_t s);
+hipError_t launch_loss(const float* yhat, const float* y, double* sq, float* dy, float* loss, int B, long long per,
+                       hipStream_t s);
+hipError_t launch_batch_sum(const float* t, float* c, int batch, long long n, hipStream_t s);
+hipError_t launch_adamw(float* w, const float* g, float* m, float* v, long long n, float lr, float b1, float b2,
+                        float eps, float wd, int t, hipStream_t s);
+
 }  // namespace dns

@@ -39,7 +39,16 @@ PREC_MIXED_FP32 = 1
 EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "dns_step",
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",
             "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
-            "dns_create_grouped", "dns_group_handle", "dns_tune"]
+            "dns_create_grouped", "dns_group_handle", "dns_tune",
+            "dns_get_channels", "dns_set_channels",
+            "sno_create", "sno_set_option", "sno_num_params", "sno_set_params", "sno_get_params",
+            "sno_forward", "sno_loss_grad", "sno_train_step", "sno_sync", "sno_last_error",
+            "sno_destroy"]
+
+SNO_MATH_BF16 = 0
+SNO_MATH_FP32 = 1
+SNO_OPT_MATH = 1
+SNO_OPT_STREAM = 2
 
 MAX_GROUPS = 16
 
@@ -58,6 +67,17 @@ class Group(ctypes.Structure):
     _fields_ = [("g", Geometry), ("Re", ctypes.c_double), ("Nx", ctypes.c_int),
                 ("Ny", ctypes.c_int), ("Nz", ctypes.c_int), ("members", ctypes.c_int),
                 ("dt", ctypes.c_double)]
+
+
+class SnoConfig(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int), ("width", ctypes.c_int), ("layers", ctypes.c_int),
+                ("Mx", ctypes.c_int), ("Mz", ctypes.c_int), ("modes_x", ctypes.c_int),
+                ("modes_z", ctypes.c_int), ("max_batch", ctypes.c_int)]
+
+
+class SnoAdamW(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("weight_decay", ctypes.c_float)]
 
 
 class Tuning(ctypes.Structure):
@@ -114,11 +134,29 @@ def library(path=LIB_PATH):
     lib.dns_create_grouped.argtypes = [ctypes.POINTER(Group), ctypes.c_int, ctypes.POINTER(vp)]
     lib.dns_group_handle.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp)]
     lib.dns_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+    lib.dns_get_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.dns_set_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.sno_create.argtypes = [ctypes.POINTER(SnoConfig), ctypes.c_ulonglong, ctypes.POINTER(vp)]
+    lib.sno_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
+    lib.sno_num_params.argtypes = [vp]
+    lib.sno_num_params.restype = ctypes.c_longlong
+    lib.sno_set_params.argtypes = [vp, vp, ctypes.c_longlong]
+    lib.sno_get_params.argtypes = [vp, vp, ctypes.c_longlong]
+    lib.sno_forward.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.sno_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), vp]
+    lib.sno_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(SnoAdamW),
+                                   ctypes.POINTER(ctypes.c_float)]
+    lib.sno_sync.argtypes = [vp]
+    lib.sno_last_error.argtypes = [vp]
+    lib.sno_last_error.restype = ctypes.c_char_p
+    lib.sno_destroy.argtypes = [vp]
+    lib.sno_destroy.restype = None
     lib.dns_host_operators.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                        _DP, _DP, _DP, _DP, _DP, _DP, _DP]
     for name in EXPORTED:
-        if name not in ("dns_destroy", "dns_last_error"):
+        if name not in ("dns_destroy", "dns_last_error", "sno_destroy", "sno_last_error",
+                        "sno_num_params"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -264,6 +302,23 @@ class Ensemble:
         out["rc"] = rc
         return out
 
+    def get_channels(self, out, member0=0):
+        """Channel form of members [member0, member0 + len(out)) into a float32
+        CUDA tensor ``out`` of shape (count, 3 Ny, Mz Mx) (include/sno.h)."""
+        self._check_channels(out)
+        return self._check(self.lib.dns_get_channels(self.h, member0, out.shape[0], out.data_ptr()))
+
+    def set_channels(self, x, member0=0):
+        """Rebuild members' states from channel-form data (float32 CUDA tensor)."""
+        self._check_channels(x)
+        return self._check(self.lib.dns_set_channels(self.h, member0, x.shape[0], x.data_ptr()))
+
+    def _check_channels(self, t):
+        P = (3 * self.Nx // 2) * (3 * self.Nz // 2)
+        if tuple(t.shape[1:]) != (3 * self.Ny, P) or str(t.dtype) != "torch.float32" \
+                or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("channel tensors are contiguous float32 CUDA (count, 3 Ny, Mz Mx)")
+
     def tune(self, cache_path=None):
         """Pick the fastest plane chunk rows and mode member tile (dns_tune)."""
         t = Tuning()
@@ -404,3 +459,81 @@ class GroupedEnsemble:
             self._check(rc)
         out["samples"], out["steps"], out["rc"] = so.samples, so.steps, rc
         return out
+
+
+class SNO:
+    """Spectral neural operator of the learned spin-up (include/sno.h).  Tensors
+    are contiguous float32 CUDA tensors of shape (batch, channels, Mx Mz)."""
+
+    def __init__(self, channels, width=32, layers=4, Mx=48, Mz=48, modes_x=12, modes_z=12,
+                 max_batch=32, seed=0):
+        self.lib = library()
+        self.cfg = SnoConfig(channels, width, layers, Mx, Mz, modes_x, modes_z, max_batch)
+        self.h = ctypes.c_void_p()
+        rc = self.lib.sno_create(ctypes.byref(self.cfg), int(seed), ctypes.byref(self.h))
+        if rc != DNS_OK:
+            raise DnsError(rc, self.lib.sno_last_error(None).decode())
+        self.num_params = int(self.lib.sno_num_params(self.h))
+
+    def _check(self, rc):
+        if rc != DNS_OK:
+            raise DnsError(rc, self.lib.sno_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if self.h:
+            self.lib.sno_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_math(self, math):
+        return self._check(self.lib.sno_set_option(self.h, SNO_OPT_MATH, int(math)))
+
+    def set_stream(self, stream):
+        handle = getattr(stream, "cuda_stream", stream)
+        return self._check(self.lib.sno_set_option(self.h, SNO_OPT_STREAM, int(handle)))
+
+    def get_params(self):
+        out = np.zeros(self.num_params, dtype=np.float32)
+        self._check(self.lib.sno_get_params(self.h, out.ctypes.data, self.num_params))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.size != self.num_params:
+            raise ValueError("parameter count mismatch")
+        return self._check(self.lib.sno_set_params(self.h, theta.ctypes.data, self.num_params))
+
+    def _t(self, t):
+        if str(t.dtype) != "torch.float32" or not t.is_cuda or not t.is_contiguous() \
+                or tuple(t.shape[1:]) != (self.cfg.channels, self.cfg.Mx * self.cfg.Mz):
+            raise ValueError("SNO tensors are contiguous float32 CUDA (batch, channels, Mx Mz)")
+        return t.data_ptr()
+
+    def forward(self, x, y):
+        return self._check(self.lib.sno_forward(self.h, self._t(x), self._t(y), x.shape[0]))
+
+    def loss_grad(self, x, target, want_grad=True):
+        loss = ctypes.c_float()
+        grad = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        self._check(self.lib.sno_loss_grad(self.h, self._t(x), self._t(target), x.shape[0],
+                                           ctypes.byref(loss),
+                                           grad.ctypes.data if want_grad else None))
+        return loss.value, grad
+
+    def train_step(self, x, target, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4,
+                   want_loss=True):
+        opt = SnoAdamW(lr, beta1, beta2, eps, weight_decay)
+        loss = ctypes.c_float()
+        self._check(self.lib.sno_train_step(self.h, self._t(x), self._t(target), x.shape[0],
+                                            ctypes.byref(opt),
+                                            ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def sync(self):
+        return self._check(self.lib.sno_sync(self.h))

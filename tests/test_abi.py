@@ -1,5 +1,5 @@
 """C ABI checks that need no GPU: the library loads, exports every function
-declared in include/dns.h, and rejects bad arguments before touching the device."""
+declared in include/*.h, and rejects bad arguments before touching the device."""
 
 import ctypes
 import os
@@ -12,13 +12,15 @@ import pytest
 from paper_2306_12739_amd import dns
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "dns.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("dns.h", "sno.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(dns_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for path in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:dns|sno)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_expected_api():
@@ -80,3 +82,19 @@ def test_grouped_arguments_rejected_without_gpu():
     assert not h.value
     sub = ctypes.c_void_p()
     assert lib.dns_group_handle(None, 0, ctypes.byref(sub)) == dns.DNS_E_STATE
+
+
+def test_sno_arguments_rejected_without_gpu():
+    lib = dns.library()
+    h = ctypes.c_void_p()
+    assert lib.sno_create(None, 1, ctypes.byref(h)) == dns.DNS_E_INVALID
+    bad = dns.SnoConfig(147, 32, 4, 48, 48, 25, 12, 8)     # modes_x > Mx / 2
+    assert lib.sno_create(ctypes.byref(bad), 1, ctypes.byref(h)) == dns.DNS_E_INVALID
+    bad = dns.SnoConfig(147, 32, 4, 48, 48, 12, 11, 8)     # odd modes_z
+    assert lib.sno_create(ctypes.byref(bad), 1, ctypes.byref(h)) == dns.DNS_E_INVALID
+    assert b"invalid" in lib.sno_last_error(None)
+    assert lib.sno_sync(None) == dns.DNS_E_STATE
+    assert lib.sno_num_params(None) == 0
+    lib.sno_destroy(None)
+    assert lib.dns_get_channels(None, 0, 1, None) == dns.DNS_E_STATE
+    assert lib.dns_set_channels(None, 0, 1, None) == dns.DNS_E_STATE
