@@ -67,6 +67,33 @@ def test_stage0_intermediates_fp64():
     gpu.close()
 
 
+@pytest.mark.parametrize("grid", [(16, 33, 0.1, "low"), (64, 97, 0.3, "k2")])
+def test_stage0_intermediates_mixed_per_field(grid):
+    """Error of the mixed-precision path against the FP64 oracle, per field:
+    velocity fields are formed in FP64 and stored in FP32; the advection terms
+    come from FP32 transforms."""
+    n, Ny, amp, spec = grid
+    flow = 0 if n == 16 else 1
+    Lx, Lz = (1.75 * np.pi, 1.2 * np.pi) if flow == 0 else (2.0 * np.pi, np.pi)
+    say(f"case: stage-0 intermediates, mixed precision, {n}x{Ny}x{n}, 2 members")
+    st = inputs.random_state(flow, Lx, Lz, n, Ny, n, 2, amp, 77, spectrum=spec)
+    gpu, ref = make_pair(flow, 400.0 if flow == 0 else 4200.0, Lx, Lz, n, Ny, n, 2, 0.01, st)
+    gpu.set_precision(dns.PREC_MIXED_FP32)
+    vel, nl, means = gpu.debug_stage0()
+    rv = ref.velocities(ref.v, ref.eta, ref.U, ref.W)
+    Nu, Nv, Nw, uv, wv = ref.nonlinear(rv)
+    errs = {f: rel(vel[i], rv[f]) for i, f in enumerate(("u", "v", "w", "uy", "wy"))}
+    errs.update({f: rel(nl[i], r) for i, (f, r) in enumerate((("Nu", Nu), ("Nv", Nv), ("Nw", Nw)))})
+    errs["<uv>"] = rel(means[0], uv)
+    errs["<wv>"] = rel(means[1], wv)
+    say("  relative 2-norm errors:", {k: f"{v:.1e}" for k, v in errs.items()})
+    for f in ("u", "v", "w", "uy", "wy"):
+        assert errs[f] <= 1e-7, f
+    for f in ("Nu", "Nv", "Nw", "<uv>", "<wv>"):
+        assert errs[f] <= 2e-6, f
+    gpu.close()
+
+
 def test_parity_couette_100_steps_fp64():
     say("case: couette 16x33x16 E=2 FP64, 100 steps dt=0.02")
     gpu, ref = cfg1_pair()

@@ -41,23 +41,6 @@ def make(E):
     return e
 
 
-def windows(ens, n):
-    """Mean and rms profiles over n consecutive windows of WIN steps."""
-    ens.set_option(dns.OPT_STATS, 1)
-    out = []
-    for _ in range(n):
-        ens.stats_reset()
-        ens.step(WIN)
-        s = ens.stats()
-        out.append({k: s[k].copy() for k in ("U", "urms", "vrms", "wrms")} | {"div": s["div_max"].max(),
-                                                                            "failed": int(s["failed"].sum())})
-    return out
-
-
-def dist(a, b):
-    return float(np.mean([np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k]) for k in ("U", "urms", "vrms", "wrms")]))
-
-
 def test_learned_spin_up_gains_over_dns_alone():
     say("case: spin-up: pairs from 64-member DNS, 8 epochs of training, 32 held-out members")
     ens = make(64)
@@ -67,28 +50,17 @@ def test_learned_spin_up_gains_over_dns_alone():
     persistence = float(((X - Y).flatten(1).norm(dim=1) / Y.flatten(1).norm(dim=1)).mean())
     net = dns.SNO(channels=X.shape[1], width=32, layers=4, Mx=48, Mz=48, modes_x=12, modes_z=12,
                   max_batch=32, seed=1)
-    hist = spinup.train(net, X, Y, epochs=8, batch=32, lr=2e-3, log=say)
+    hist = spinup.train(net, (X, Y), epochs=8, batch=32, lr=2e-3, log=say)
     say(f"persistence loss {persistence:.4f}, trained {hist[-1]:.4f}")
     assert hist[-1] < 0.9 * persistence
 
     held = inputs.workload_state(NAME, ensemble=32, seed=3001)
-    ref = make(32)
-    ref.set_state(*held)
-    R = windows(ref, 12)
-    ref.close()
-    sno_arm = make(32)
-    sno_arm.set_state(*held)
-    spinup.spin_up(sno_arm, net, APPS)
-    S = windows(sno_arm, 8)
-    sno_arm.close()
+    d_s, d_0, S, rejected = spinup.gain(make, net, held, APPS, GAP, WIN, 8)
     net.close()
-    skip = APPS * GAP // WIN
-    d_s = [dist(S[h], R[h + skip]) for h in range(8)]
-    d_0 = [dist(R[h], R[h + skip]) for h in range(8)]
     say("distance to the DNS-only ensemble 400 steps ahead, per window:")
     say("  spun up :", [round(x, 3) for x in d_s])
     say("  DNS only:", [round(x, 3) for x in d_0])
-    assert all(w["failed"] == 0 for w in S)
+    assert rejected == 0 and all(w["failed"] == 0 for w in S)
     assert max(w["div"] for w in S) <= 1e-6
     # measured: mean 0.176 vs 0.228, first window 0.208 vs 0.286
     assert np.mean(d_s) < 0.9 * np.mean(d_0)
