@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "3xbf16"], default="mixed")
     ap.add_argument("--workload", default="channel-re4200-64x97x64-e16")
     ap.add_argument("--ensemble", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true")
@@ -148,7 +148,8 @@ def main():
     stream = torch.cuda.Stream()
     ens = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], E, w["dt"])
     ens.set_stream(stream)
-    ens.set_precision(dns.PREC_FP64 if args.precision == "fp64" else dns.PREC_MIXED_FP32)
+    ens.set_precision({"fp64": dns.PREC_FP64, "mixed": dns.PREC_MIXED_FP32,
+                       "3xbf16": dns.PREC_MIXED_3XBF16}[args.precision])
     ens.set_option(dns.OPT_GRAPH, 0 if args.no_graph else 1)
     ens.set_state(*inputs.workload_state(name, ensemble=E))
     tuning = None if args.no_tune else ens.tune()
@@ -213,7 +214,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "dtype": {"mixed": "f32+f64", "3xbf16": "f32+bf16x3+f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": name, "flow": "poiseuille" if w["flow"] else "couette",
                    "Re": w["Re"], "grid": f"{w['Nx']}x{w['Ny']}x{w['Nz']}", "ensemble": E,

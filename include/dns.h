@@ -115,9 +115,13 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  1, 2, 4 or 8, fitting 160 KB of LDS           */
 
 #define DNS_PREC_FP64 0        /* every stage in FP64                               */
-#define DNS_PREC_MIXED_FP32 1  /* y-derivative products and x-z FFTs in FP32, FP32
-                                  stage buffers; implicit solves, mean flow and
-                                  flux update in FP64                              */
+#define DNS_PREC_MIXED_FP32 1  /* x-z FFTs and advection products in FP32, FP32
+                                  stage buffers; y-derivative products, implicit
+                                  solves, mean flow and flux update in FP64       */
+#define DNS_PREC_MIXED_3XBF16 2 /* as DNS_PREC_MIXED_FP32, with the y-derivative
+                                  products (D1 and the clamped D1c) on BF16
+                                  matrix cores as three split products
+                                  (hi*hi + hi*lo + lo*hi, FP32 accumulation)       */
 
 /* Set an option.  Precision may be changed between steps (the stage buffers
  * are re-derived from the FP64 state).  Errors: DNS_E_INVALID. */

@@ -49,6 +49,7 @@ struct dns_handle {
   size_t op_group_stride = 0;
   double *D1intT_e = nullptr, *D1intT_o = nullptr, *D1cT_e = nullptr, *D1cT_o = nullptr;
   double *D1T_e = nullptr, *D1T_o = nullptr;
+  unsigned short *Dhi[6] = {}, *Dlo[6] = {};  // split-BF16 tiles of the six derivative halves
   int CRP = 16, SR = 0, TR = 0;
   double *lift_h[2] = {nullptr, nullptr}, *green_h[2] = {nullptr, nullptr};
   double *ccw_h = nullptr, *D1 = nullptr, *ccw = nullptr;
@@ -130,6 +131,10 @@ void free_all(dns_handle* h) {
                   h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging};
   for (void* p : bufs)
     if (p) hipFree(p);
+  for (int i = 0; i < 6; ++i) {
+    if (h->Dhi[i]) hipFree(h->Dhi[i]);
+    if (h->Dlo[i]) hipFree(h->Dlo[i]);
+  }
   if (h->own_stream) hipStreamDestroy(h->own_stream);
 }
 
@@ -167,6 +172,10 @@ ModeArgs mode_args(dns_handle* h, int stage) {
   a.D1cT_o = h->D1cT_o;
   a.D1T_e = h->D1T_e;
   a.D1T_o = h->D1T_o;
+  for (int i = 0; i < 6; ++i) {
+    a.Dhi[i] = h->Dhi[i];
+    a.Dlo[i] = h->Dlo[i];
+  }
   a.lift_h = h->lift_h[hi];
   a.green_h = h->green_h[hi];
   a.ccw_h = h->ccw_h;
@@ -500,10 +509,15 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     lift_h[hi] = halves(ho.lift[hi]);
     green_h[hi] = halves(ho.green[hi]);
   }
-  // derivative halves: even input -> odd output and odd input -> even output
+  // derivative halves: even input -> odd output and odd input -> even output,
+  // FP64 tiles and split-BF16 tiles (index order of ModeArgs::Dhi)
+  std::vector<unsigned short> bhi[6], blo[6];
+  int nsplit = 0;
   auto dhalf = [&](const double* M, int rows_out, int Cn, int ldm, bool even_in) {
     const std::vector<double> b = half_block(M, rows_out, Cn, ldm, even_in);
     const int ncol = even_in ? (Cn + 1) / 2 : Cn / 2;
+    tile_for_mfma_bf16(b.data(), rows_out, ncol, ncol, &bhi[nsplit], &blo[nsplit]);
+    ++nsplit;
     return tile_for_mfma(b.data(), rows_out, ncol, ncol);
   };
   const double* D1int = ho.D1.data() + My;  // interior rows of D1
@@ -529,6 +543,10 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   ALLOC(h->D1T_e, D1T_e.size());
   ALLOC(h->D1T_o, D1T_o.size());
   ALLOC(h->ccw_h, ccw_h.size());
+  for (int i = 0; i < 6; ++i) {
+    ALLOC(h->Dhi[i], bhi[i].size());
+    ALLOC(h->Dlo[i], blo[i].size());
+  }
   ALLOC(h->D1, ho.D1.size());
   ALLOC(h->ccw, ho.ccw.size());
   ALLOC(h->gamma, size_t(h->E));
@@ -558,6 +576,10 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   ok &= up(h->D1T_e, D1T_e) == hipSuccess;
   ok &= up(h->D1T_o, D1T_o) == hipSuccess;
   ok &= up(h->ccw_h, ccw_h) == hipSuccess;
+  for (int i = 0; i < 6; ++i) {
+    ok &= hipMemcpy(h->Dhi[i], bhi[i].data(), bhi[i].size() * 2, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(h->Dlo[i], blo[i].data(), blo[i].size() * 2, hipMemcpyHostToDevice) == hipSuccess;
+  }
   ok &= up(h->D1, ho.D1) == hipSuccess;
   ok &= up(h->ccw, ho.ccw) == hipSuccess;
   // laminar state, zero history
@@ -652,7 +674,7 @@ int dns_set_option(dns_handle* h, int key, long long value) {
   }
   switch (key) {
     case DNS_OPT_PRECISION:
-      if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32)
+      if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32 && value != DNS_PREC_MIXED_3XBF16)
         return fail(h, DNS_E_INVALID, "unknown precision");
       if (value != h->precision) {
         h->precision = int(value);

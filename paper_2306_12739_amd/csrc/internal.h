@@ -62,6 +62,11 @@ struct ModeArgs {
   const double* D1cT_o;    // odd interior half -> even full half (Fe x Ho)
   const double* D1T_e;     // D1: even full half -> odd full half (Fo x Fe)
   const double* D1T_o;     // odd full half -> even full half (Fe x Fo)
+  // the same six derivative halves as bfloat16 pairs (hi + lo), tiled for
+  // v_mfma_f32_16x16x16bf16_1k (see tile_for_mfma_bf16); used by the split-BF16
+  // precision, index order D1int_e, D1int_o, D1c_e, D1c_o, D1_e, D1_o
+  const unsigned short* Dhi[6];
+  const unsigned short* Dlo[6];
   const double* lift_h;    // [N]: even half (He) then odd half (Ho) of the Couette lift
   const double* green_h;   // [N]: halves of the pressure-gradient response
   const double* ccw_h;     // [Fe]: Clenshaw-Curtis weights summed over node pairs
@@ -86,6 +91,13 @@ bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
 int mode_member_tile(int My, int E);
 void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR);
+
+// Row-major R x Kd matrix -> bfloat16 A-operand tiles of the 16x16x16 BF16 MFMA,
+// split M = hi + lo (each rounded to nearest even): tile (rt, kt), kt <
+// ceil(Kd/16), is 64 lanes x 4 values, lane l holding M[16 rt + l % 16][16 kt +
+// 4 (l / 16) + t], t < 4 (zero outside the matrix).
+void tile_for_mfma_bf16(const double* M, int R, int Kd, int ldm, std::vector<unsigned short>* hi,
+                        std::vector<unsigned short>* lo);
 
 // Row-major R x Kd matrix (row stride ldm) -> MFMA A-operand tiles: tile
 // (rt, kt), rt < ceil(R/16), kt < ceil(Kd/4), is 64 consecutive values with

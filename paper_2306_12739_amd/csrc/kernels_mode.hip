@@ -29,6 +29,9 @@
 // 4).  Matrices are stored pre-tiled in the MFMA A lane order (tile (rt, kt) =
 // 64 consecutive doubles, lane l holding M[16 rt + l % 16][4 kt + l / 16]), so
 // each A fragment is one coalesced 512 B load; X lives in LDS as [k][column].
+// With the split-BF16 precision the six y-derivative contractions instead run
+// as three bfloat16 products on v_mfma_f32_16x16x16bf16_1k (the solves stay
+// FP64).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -82,6 +85,66 @@ __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int
   }
 }
 
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return static_cast<short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(short h) {
+  return __uint_as_float(static_cast<unsigned int>(static_cast<unsigned short>(h)) << 16);
+}
+
+// Split-BF16 variant of mfma_contract: M = Mhi + Mlo (pre-tiled bfloat16 pairs,
+// K in steps of 16), X rounded to FP32 and split the same way on the fly;
+// M X ~ Mhi Xhi + Mhi Xlo + Mlo Xhi on v_mfma_f32_16x16x16bf16_1k with FP32
+// accumulation (the Mlo Xlo term is below FP32 resolution).  X needs 16 KT
+// finite rows.  D layout: lane l, register r -> row 4 (l / 16) + r, col l % 16.
+template <class Store>
+__device__ __forceinline__ void mfma_contract_split(const unsigned short* __restrict__ Hi,
+                                                    const unsigned short* __restrict__ Lo, int RT, int KT,
+                                                    const double* X, int ldx, int CT, Store store) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = (lane >> 4) * 4;
+  for (int t = wave; t < RT * CT; t += kWaves) {
+    const int rt = t / CT, ct = t - rt * CT;
+    const bf16x4* ah = reinterpret_cast<const bf16x4*>(Hi) + size_t(rt) * KT * 64 + lane;
+    const bf16x4* al = reinterpret_cast<const bf16x4*>(Lo) + size_t(rt) * KT * 64 + lane;
+    const double* b = X + lk * ldx + ct * 16 + lr;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < KT; ++kt) {
+      const bf16x4 a_hi = ah[kt * 64], a_lo = al[kt * 64];
+      bf16x4 b_hi, b_lo;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float x = float(b[(16 * kt + q) * ldx]);
+        const short h = bf16_bits(x);
+        b_hi[q] = h;
+        b_lo[q] = bf16_bits(x - bf16_value(h));
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_hi, b_hi, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_hi, b_lo, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_lo, b_hi, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(rt * 16 + lk + r, ct * 16 + lr, double(acc[r]));
+  }
+}
+
+// A y-derivative contraction (one of the six parity halves, index `which`):
+// FP64 matrix cores, or the split-BF16 variant.  Kd is the K dimension.
+template <bool kSplit, class Store>
+__device__ __forceinline__ void dcontract(const ModeArgs& a, int which, const double* Mt, int RT, int Kd,
+                                          const double* X, int ldx, int CT, Store store) {
+  if constexpr (kSplit)
+    mfma_contract_split(a.Dhi[which], a.Dlo[which], RT, (Kd + 15) / 16, X, ldx, CT, store);
+  else
+    mfma_contract(Mt, RT, (Kd + 3) / 4, X, ldx, CT, store);
+}
+
 template <typename VT>
 __device__ __forceinline__ void st_c(VT* p, double re, double im) {
   p[0] = VT(re);
@@ -99,7 +162,7 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 //   S  : solve stack [v0_e; F'_e; v0_o; F'_o] (interior halves), later eta (FH)
 //   S2 : solve stack [eta0_e; G'_e; eta0_o; G'_o], later dv/dy, u, dw/dy (FH)
 //   T  : Q = i kx N_u + i kz N_w (FH), later v (FH), later du/dy (FH)
-template <typename VT>
+template <typename VT, bool kSplit>
 __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
@@ -147,7 +210,6 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   // tile counts of the half-size matrices
   const int RTe = (He + 15) / 16, RTo = (Ho + 15) / 16, RFe = (Fe + 15) / 16, RFo = (Fo + 15) / 16;
   const int KSe = (2 * He + 3) / 4, KSo = (2 * Ho + 3) / 4;
-  const int KFe = (Fe + 3) / 4, KFo = (Fo + 3) / 4, KHe = (He + 3) / 4, KHo = (Ho + 3) / 4;
 
   // write the FH pair k of buffer B (re/im columns 2c, 2c+1) to stage field f
   auto write_pair = [&](const double* B, int k, int c, int f) {
@@ -205,10 +267,10 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       }
       __syncthreads();
       // F = -k^2 N_v - D1 Q: odd F from even Q, even F from odd Q
-      mfma_contract(a.D1intT_e, RTo, KFe, T, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kSplit>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
         if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
       });
-      mfma_contract(a.D1intT_o, RTe, KFo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kSplit>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < He) S[(He + r) * CRP + cc] -= v;
       });
       __syncthreads();
@@ -366,10 +428,10 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     }
     __syncthreads();
     // ---- velocity recovery: dv/dy = D1c v (odd <- even, even <- odd) -> S2 FH
-    mfma_contract(a.D1cT_e, RFo, KHe, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
     });
-    mfma_contract(a.D1cT_o, RFe, KHo, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < Fe) S2[r * CRP + cc] = v;
     });
     __syncthreads();
@@ -416,17 +478,17 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     }
     __syncthreads();
     // du/dy = D1 u -> T (FH); then dw/dy = D1 w -> S2 (FH)
-    mfma_contract(a.D1T_e, RFo, KFe, S2, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
       if (r < Fo) T[(Fe + r) * CRP + cc] = v;
     });
-    mfma_contract(a.D1T_o, RFe, KFo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < Fe) T[r * CRP + cc] = v;
     });
     __syncthreads();
-    mfma_contract(a.D1T_e, RFo, KFe, S, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
       if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
     });
-    mfma_contract(a.D1T_o, RFe, KFo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < Fe) S2[r * CRP + cc] = v;
     });
     __syncthreads();
@@ -473,10 +535,10 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     }
     __syncthreads();
     // (E_U, E_W) = -D1 (<uv>, <wv>) on interior halves
-    mfma_contract(a.D1intT_e, RTo, KFe, T, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
       if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] = -v;
     });
-    mfma_contract(a.D1intT_o, RTe, KFo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kSplit>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < He) S[(He + r) * CRP + cc] = -v;
     });
     __syncthreads();
@@ -600,10 +662,10 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   }
   __syncthreads();
   // (0,0) velocity fields: u = U, v = 0, w = W, du/dy = D1 U, dw/dy = D1 W
-  mfma_contract(a.D1T_e, RFo, KFe, T, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
     if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
   });
-  mfma_contract(a.D1T_o, RFe, KFo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
     if (r < Fe) S2[r * CRP + cc] = v;
   });
   __syncthreads();
@@ -633,16 +695,17 @@ void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR) {
   const int N = My - 2;
   const int He = (N + 1) / 2, Ho = N / 2, Fe = He + 1, Fo = Ho + 1;
   auto t4 = [](int n) { return 4 * ((n + 3) / 4); };
+  auto t16 = [](int n) { return 16 * ((n + 15) / 16); };  // K steps of the split-BF16 contractions
   auto mx = [](int a, int b) { return a > b ? a : b; };
   *CRP = ((4 * ET + 15) / 16) * 16;
   // S/S2: even solve reads rows < t4(2He), odd solve from 2He; D1 halves read
-  // rows < t4(Fe) and from Fe
+  // rows < t16(Fe) and from Fe
   int sr = mx(t4(2 * He), 2 * He + t4(2 * Ho));
-  sr = mx(sr, Fe + t4(Fo));
-  sr = mx(sr, mx(t4(Fe), My));
+  sr = mx(sr, Fe + t16(Fo));
+  sr = mx(sr, mx(t16(Fe), My));
   // T: D1int/D1 halves as above; D1c halves from row 1 and from row Fe + 1
-  int tr = mx(Fe + t4(Fo), t4(Fe));
-  tr = mx(tr, mx(1 + t4(He), Fe + 1 + t4(Ho)));
+  int tr = mx(Fe + t16(Fo), t16(Fe));
+  tr = mx(tr, mx(1 + t16(He), Fe + 1 + t16(Ho)));
   *SR = sr;
   *TR = mx(tr, My);
 }
@@ -662,14 +725,19 @@ int mode_member_tile(int My, int E) {
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   const int nblk = a.G * a.ntiles;
   const size_t lds = size_t(2 * a.SR + a.TR) * a.CRP * sizeof(double);
-  const void* fn = precision == 0 ? reinterpret_cast<const void*>(&mode_kernel<double>)
-                                  : reinterpret_cast<const void*>(&mode_kernel<float>);
+  // precision 0: FP64 stage buffers; 1: FP32 stage buffers; 2: FP32 stage
+  // buffers and split-BF16 derivative contractions
+  const void* fn = precision == 0   ? reinterpret_cast<const void*>(&mode_kernel<double, false>)
+                   : precision == 1 ? reinterpret_cast<const void*>(&mode_kernel<float, false>)
+                                    : reinterpret_cast<const void*>(&mode_kernel<float, true>);
   hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (err != hipSuccess) return err;
   if (precision == 0) {
-    hipLaunchKernelGGL(mode_kernel<double>, dim3(nblk), dim3(kNT), lds, s, a);
+    hipLaunchKernelGGL((mode_kernel<double, false>), dim3(nblk), dim3(kNT), lds, s, a);
+  } else if (precision == 1) {
+    hipLaunchKernelGGL((mode_kernel<float, false>), dim3(nblk), dim3(kNT), lds, s, a);
   } else {
-    hipLaunchKernelGGL(mode_kernel<float>, dim3(nblk), dim3(kNT), lds, s, a);
+    hipLaunchKernelGGL((mode_kernel<float, true>), dim3(nblk), dim3(kNT), lds, s, a);
   }
   return hipGetLastError();
 }

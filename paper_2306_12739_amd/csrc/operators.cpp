@@ -15,6 +15,7 @@
 // Eq. (CN2): A_eta = (I - c Lap)^{-1} (I + c Lap), B_eta = (I - c Lap)^{-1}.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <thread>
 #include <vector>
 
@@ -226,6 +227,40 @@ std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm) {
         if (r < R && k < Kd) out[(size_t(rt) * KT + kt) * 64 + l] = M[size_t(r) * ldm + k];
       }
   return out;
+}
+
+namespace {
+unsigned short bf16_rne(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<unsigned short>(u >> 16);
+}
+float bf16_value(unsigned short h) {
+  const unsigned int u = static_cast<unsigned int>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+}  // namespace
+
+void tile_for_mfma_bf16(const double* M, int R, int Kd, int ldm, std::vector<unsigned short>* hi,
+                        std::vector<unsigned short>* lo) {
+  const int RT = (R + 15) / 16, KT = (Kd + 15) / 16;
+  hi->assign(size_t(RT) * KT * 256, 0);
+  lo->assign(size_t(RT) * KT * 256, 0);
+  for (int rt = 0; rt < RT; ++rt)
+    for (int kt = 0; kt < KT; ++kt)
+      for (int l = 0; l < 64; ++l)
+        for (int t = 0; t < 4; ++t) {
+          const int r = rt * 16 + l % 16, k = kt * 16 + 4 * (l / 16) + t;
+          if (r >= R || k >= Kd) continue;
+          const double m = M[size_t(r) * ldm + k];
+          const unsigned short h = bf16_rne(float(m));
+          const size_t o = ((size_t(rt) * KT + kt) * 64 + l) * 4 + t;
+          (*hi)[o] = h;
+          (*lo)[o] = bf16_rne(float(m - double(bf16_value(h))));
+        }
 }
 
 std::vector<double> half_block(const double* M, int rows_out, int Cn, int ldm, bool even_in) {

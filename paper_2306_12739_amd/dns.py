@@ -35,6 +35,7 @@ OPT_MODE_TILE = 6
 
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1
+PREC_MIXED_3XBF16 = 2
 
 EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "dns_step",
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",

@@ -67,18 +67,19 @@ def test_stage0_intermediates_fp64():
     gpu.close()
 
 
+@pytest.mark.parametrize("precision", [dns.PREC_MIXED_FP32, dns.PREC_MIXED_3XBF16])
 @pytest.mark.parametrize("grid", [(16, 33, 0.1, "low"), (64, 97, 0.3, "k2")])
-def test_stage0_intermediates_mixed_per_field(grid):
-    """Error of the mixed-precision path against the FP64 oracle, per field:
-    velocity fields are formed in FP64 and stored in FP32; the advection terms
-    come from FP32 transforms."""
+def test_stage0_intermediates_mixed_per_field(grid, precision):
+    """Error of the mixed-precision paths against the FP64 oracle, per field:
+    velocity fields are formed with FP64 (or split-BF16) y-derivative products
+    and stored in FP32; the advection terms come from FP32 transforms."""
     n, Ny, amp, spec = grid
     flow = 0 if n == 16 else 1
     Lx, Lz = (1.75 * np.pi, 1.2 * np.pi) if flow == 0 else (2.0 * np.pi, np.pi)
-    say(f"case: stage-0 intermediates, mixed precision, {n}x{Ny}x{n}, 2 members")
+    say(f"case: stage-0 intermediates, precision {precision}, {n}x{Ny}x{n}, 2 members")
     st = inputs.random_state(flow, Lx, Lz, n, Ny, n, 2, amp, 77, spectrum=spec)
     gpu, ref = make_pair(flow, 400.0 if flow == 0 else 4200.0, Lx, Lz, n, Ny, n, 2, 0.01, st)
-    gpu.set_precision(dns.PREC_MIXED_FP32)
+    gpu.set_precision(precision)
     vel, nl, means = gpu.debug_stage0()
     rv = ref.velocities(ref.v, ref.eta, ref.U, ref.W)
     Nu, Nv, Nw, uv, wv = ref.nonlinear(rv)
@@ -87,10 +88,13 @@ def test_stage0_intermediates_mixed_per_field(grid):
     errs["<uv>"] = rel(means[0], uv)
     errs["<wv>"] = rel(means[1], wv)
     say("  relative 2-norm errors:", {k: f"{v:.1e}" for k, v in errs.items()})
+    # split-BF16: the products accumulate in FP32, and D1 at Ny = 97 has entries
+    # ~ (Ny-1)^2 / 3, so y-derivatives carry ~1e-3 relative error (measured 1.1e-3)
+    split = precision == dns.PREC_MIXED_3XBF16
     for f in ("u", "v", "w", "uy", "wy"):
-        assert errs[f] <= 1e-7, f
+        assert errs[f] <= (3e-3 if split else 1e-7), f
     for f in ("Nu", "Nv", "Nw", "<uv>", "<wv>"):
-        assert errs[f] <= 2e-6, f
+        assert errs[f] <= (3e-3 if split else 2e-6), f
     gpu.close()
 
 
@@ -308,10 +312,11 @@ def test_time_averaged_statistics_match_oracle():
     gpu.close()
 
 
-def test_mixed_precision_error_is_small():
-    say("case: MIXED_FP32 couette 16x33x16, 100 steps; errors vs FP64 oracle")
+@pytest.mark.parametrize("precision", [dns.PREC_MIXED_FP32, dns.PREC_MIXED_3XBF16])
+def test_mixed_precision_error_is_small(precision):
+    say(f"case: precision {precision}, couette 16x33x16, 100 steps; errors vs FP64 oracle")
     gpu, ref = cfg1_pair()
-    gpu.set_precision(dns.PREC_MIXED_FP32)
+    gpu.set_precision(precision)
     vel, nl, means = gpu.debug_stage0()
     rv = ref.velocities(ref.v, ref.eta, ref.U, ref.W)
     Nu, Nv, Nw, uv, wv = ref.nonlinear(rv)
@@ -321,6 +326,7 @@ def test_mixed_precision_error_is_small():
     ref.step(100)
     errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
     say("mixed errors after 100 steps:", errs)
-    assert max(e_stage.values()) <= 1e-5
-    assert max(errs.values()) <= 1e-4
+    split = precision == dns.PREC_MIXED_3XBF16
+    assert max(e_stage.values()) <= (1e-4 if split else 1e-5)
+    assert max(errs.values()) <= (1e-3 if split else 1e-4)
     gpu.close()

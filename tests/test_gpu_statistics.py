@@ -60,16 +60,20 @@ def compare(a, b):
 
 @pytest.mark.parametrize("name", ["couette-re600-32x49x32-e64", "channel-re4200-64x97x64-e16"])
 def test_mixed_statistics_match_fp64(name):
-    say(f"case: statistics {name}: FP64, mixed, FP64 with another seed")
+    say(f"case: statistics {name}: FP64, mixed, split-BF16, FP64 with another seed")
     ref = run(name, dns.PREC_FP64)
     mix = run(name, dns.PREC_MIXED_FP32)
+    spl = run(name, dns.PREC_MIXED_3XBF16)
     other = run(name, dns.PREC_FP64, seed=inputs.WORKLOADS[name]["seed"] + 100)
     d_mix = compare(mix, ref)
+    d_spl = compare(spl, ref)
     d_seed = compare(other, ref)
-    rec = {"workload": name, "mixed_vs_fp64": d_mix, "fp64_seed_to_seed": d_seed,
-           "re_tau_fp64": ref["re_tau"], "re_tau_mixed": mix["re_tau"],
+    rec = {"workload": name, "mixed_vs_fp64": d_mix, "split_bf16_vs_fp64": d_spl,
+           "fp64_seed_to_seed": d_seed,
+           "re_tau_fp64": ref["re_tau"], "re_tau_mixed": mix["re_tau"], "re_tau_split": spl["re_tau"],
            "seconds_fp64": ref["seconds"], "seconds_mixed": mix["seconds"],
-           "failed": int(ref["failed"].sum() + mix["failed"].sum())}
+           "seconds_split": spl["seconds"],
+           "failed": int(ref["failed"].sum() + mix["failed"].sum() + spl["failed"].sum())}
     say(json.dumps(rec))
     os.makedirs(OUT, exist_ok=True)
     with open(os.path.join(OUT, f"stats_{name}.json"), "w") as f:
@@ -77,3 +81,4 @@ def test_mixed_statistics_match_fp64(name):
     assert rec["failed"] == 0
     for k in ("U", "urms", "vrms", "wrms", "tau_w"):
         assert d_mix[k] <= 0.01, (k, d_mix[k])
+        assert d_spl[k] <= 0.01, (k, d_spl[k])
