@@ -104,6 +104,9 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
+// static LDS of the per-mode kernel (reduction scratch and per-member gamma)
+constexpr size_t kModeStaticLds = 2560;
+
 size_t vt_size(int precision) { return precision == DNS_PREC_FP64 ? sizeof(double) : sizeof(float); }
 
 void destroy_one(dns_handle* h);
@@ -403,6 +406,13 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     return fail(nullptr, dc, "need even Nx, Nz > 0, 5 <= Ny <= 257 and ensemble >= 1");
   if (dc == DNS_E_UNSUPPORTED)
     return fail(nullptr, dc, "grid not built: Nx == Nz in {16, 32, 48, 64} are supported");
+  {
+    // one member per per-mode workgroup must fit the workgroup LDS (Ny <= 252)
+    int crp, sr, tr;
+    mode_lds_geometry(Ny, 1, &crp, &sr, &tr);
+    if (size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds > 160 * 1024)
+      return fail(nullptr, DNS_E_UNSUPPORTED, "Ny too large: the per-mode kernel's LDS holds Ny <= 252");
+  }
 
   dns_handle* h = new dns_handle();
   h->flow = g->flow;

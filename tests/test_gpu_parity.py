@@ -98,6 +98,44 @@ def test_stage0_intermediates_mixed_per_field(grid, precision):
     gpu.close()
 
 
+@pytest.mark.parametrize("case", [
+    (0, 16, 32, 3, 20),    # even Ny: the y-parity halves have no centre node
+    (1, 32, 40, 2, 10),    # even Ny, channel (flux constraint on even halves)
+    (0, 16, 5, 2, 10),     # the smallest grid, N = 3
+    (1, 32, 49, 1, 10),    # a single member
+], ids=["couette-16x32-e3", "channel-32x40-e2", "couette-16x5-e2", "channel-32x49-e1"])
+def test_parity_edge_grids_fp64(case):
+    flow, n, Ny, E, steps = case
+    Lx, Lz = (1.75 * np.pi, 1.2 * np.pi) if flow == 0 else (2.0 * np.pi, np.pi)
+    Re, dt = (400.0, 0.02) if flow == 0 else (2000.0, 0.01)
+    say(f"case: edge grid flow={flow} {n}x{Ny}x{n} E={E}, {steps} steps FP64")
+    st = inputs.random_state(flow, Lx, Lz, n, Ny, n, E, 0.1, 31, spectrum="k2")
+    gpu, ref = make_pair(flow, Re, Lx, Lz, n, Ny, n, E, dt, st)
+    gpu.step(steps)
+    ref.step(steps)
+    errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
+    say("  errors:", errs)
+    for k, e in errs.items():
+        assert e <= 1e-10, (k, e)
+    gpu.close()
+
+
+def test_largest_ny_runs_at_the_lds_limit():
+    say("case: Couette 16x252x16 (largest Ny), laminar fixed point and a perturbed member, FP64")
+    Lx, Lz = 1.75 * np.pi, 1.2 * np.pi
+    gpu = dns.Ensemble(0, 400.0, Lx, Lz, 16, 252, 16, 2, 0.005)
+    v, eta, U, W = gpu.get_state()
+    lam = U.copy()
+    st = inputs.random_state(0, Lx, Lz, 16, 252, 16, 1, 0.05, 5, spectrum="low")
+    gpu.set_state(*st, member0=1)
+    gpu.step(5)
+    v, eta, U, W = gpu.get_state()
+    assert np.abs(U[0] - lam[0]).max() <= 1e-10 and np.abs(v[0]).max() == 0.0
+    assert np.all(np.isfinite(v[1])) and np.all(np.isfinite(U[1]))
+    assert gpu.stats()["div_max"][1] <= 1e-8
+    gpu.close()
+
+
 def test_parity_couette_100_steps_fp64():
     say("case: couette 16x33x16 E=2 FP64, 100 steps dt=0.02")
     gpu, ref = cfg1_pair()
