@@ -183,6 +183,35 @@ template <> struct Split<144> { static constexpr int A = 12, B = 12; };
 // output element k of sequence b exactly once.  mid holds NBATCH * MidPitch<N>
 // elements; root[t] = e^{-2 pi i t / N}.  One barrier separates the passes; the
 // caller places barriers around the call when load/store touch shared memory.
+// Most lanes of one wavefront that meet in one LDS bank when lane l touches
+// element (l / G) * S + l % G of W 4-byte words, for NB banks of 4 bytes.
+constexpr int lds_bank_load(int S, int G, int W, int NB) {
+  int cnt[64] = {};
+  int mx = 0;
+  for (int l = 0; l < 64; ++l) {
+    const int e = (l / G) * S + l % G;
+    for (int w = 0; w < W; ++w) {
+      const int b = (e * W + w) % NB;
+      if (++cnt[b] > mx) mx = cnt[b];
+    }
+  }
+  return mx;
+}
+
+// Row pitch in [base, base + 16] with the fewest bank collisions for rows read
+// in groups of G1 (and G2, if non-zero) consecutive lanes, under 32 and 64 banks;
+// each extra element of pitch costs a quarter of a collision.
+constexpr int lds_pitch(int base, int G1, int G2, int W) {
+  int best = base, load = 1 << 30;
+  for (int s = base; s <= base + 16; ++s) {
+    int v = lds_bank_load(s, G1, W, 32) + lds_bank_load(s, G1, W, 64);
+    if (G2) v += lds_bank_load(s, G2, W, 32) + lds_bank_load(s, G2, W, 64);
+    v = 4 * v + (s - base);
+    if (v < load) load = v, best = s;
+  }
+  return best;
+}
+
 template <int N>
 struct MidPitch {
   static constexpr int row = Split<N>::B + 1;
@@ -190,7 +219,10 @@ struct MidPitch {
   static constexpr int value = (raw % 2) ? raw : raw + 1;
 };
 
-template <typename T, int N, int DIR, int NBATCH, int NT, class Load, class Store>
+// kBatchFast selects which index consecutive threads step through: the
+// butterfly index within a sequence (false) or the sequence index (true).  The
+// caller picks the one along which its load/store addresses are contiguous.
+template <typename T, int N, int DIR, int NBATCH, int NT, bool kBatchFast = false, class Load, class Store>
 __device__ __forceinline__ void fft2pass(cx<T>* mid, const cx<T>* root, Load load, Store store) {
   constexpr int RA = Split<N>::A;
   constexpr int RB = Split<N>::B;
@@ -199,7 +231,8 @@ __device__ __forceinline__ void fft2pass(cx<T>* mid, const cx<T>* root, Load loa
   const int tid = threadIdx.x;
 #pragma unroll 1
   for (int it = tid; it < NBATCH * RB; it += NT) {
-    const int b = it / RB, j = it - b * RB;
+    const int b = kBatchFast ? it % NBATCH : it / RB;
+    const int j = kBatchFast ? it / NBATCH : it - b * RB;
     cx<T> v[RA];
 #pragma unroll
     for (int r = 0; r < RA; ++r) v[r] = load(b, j + r * RB);
@@ -210,7 +243,8 @@ __device__ __forceinline__ void fft2pass(cx<T>* mid, const cx<T>* root, Load loa
   __syncthreads();
 #pragma unroll 1
   for (int it = tid; it < NBATCH * RA; it += NT) {
-    const int b = it / RA, k = it - b * RA;
+    const int b = kBatchFast ? it % NBATCH : it / RA;
+    const int k = kBatchFast ? it / NBATCH : it - b * RA;
     cx<T> v[RB];
 #pragma unroll
     for (int t = 0; t < RB; ++t) v[t] = mid[b * SP + k * RP + t];

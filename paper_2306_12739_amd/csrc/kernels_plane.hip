@@ -72,18 +72,22 @@ template <typename T, int L, int P, int PP>
 struct PlaneCfg {
   static constexpr int MX = 3 * L, MZ = 3 * P, NZ = 2 * P - 1;
   static constexpr int R = MZ / PP, PH = PP / 2;
-  // LDS pitches (odd, to spread consecutive rows over the banks)
-  static constexpr int ZP = L + 1;                             // z-transform output rows [q][nx]
-  static constexpr int FP = 2 * L + 1;                         // forward x rows [pair][kx]
-  static constexpr int ZB0 = 3 * PP * ZP, ZB1 = 3 * PH * FP, ZB2 = 3 * L * PP;
+  static constexpr int RAX = Split<MX>::A, RBX = Split<MX>::B;
+  // LDS pitches, chosen so that the lanes of a wavefront spread over the banks
+  static constexpr int ZP = L + 1;                             // z-transform rows [q][nx]
+  static constexpr int FP = lds_pitch(2 * L, RAX, 0, 2);       // forward x rows [pair][kx]
+  static constexpr int MXP = lds_pitch(MX, RAX, RBX, 1);       // physical rows [q][x]
+  static constexpr int PPP = lds_pitch(PP, 1, 0, 2);           // forward z output [(f, nx)][k]
+  static constexpr int ZB0 = 3 * PP * ZP, ZB1 = 3 * PH * FP, ZB2 = 3 * L * PPP;
   static constexpr int ZB = ZB0 > ZB1 ? (ZB0 > ZB2 ? ZB0 : ZB2) : (ZB1 > ZB2 ? ZB1 : ZB2);
   static constexpr int MIDZ = 3 * L * MidPitch<PP>::value, MIDX = 3 * PH * MidPitch<MX>::value;
   static constexpr int MID = MIDZ > MIDX ? MIDZ : MIDX;
   static constexpr int NPT = PP * MX;                          // physical points per chunk
+  static constexpr int NPTS = PP * MXP;                        // their LDS footprint per field
   static constexpr int NACC = (3 * L * NZ + kNT - 1) / kNT;
   // static LDS of plane_kernel: roots, zb, mid, phys and the reduction scratch
   static constexpr size_t kLdsBytes =
-      (MX + MZ + PP + ZB + MID) * 2 * sizeof(T) + NPHYS * NPT * sizeof(T) + 8 * (kNT / 64) * sizeof(double);
+      (MX + MZ + PP + ZB + MID) * 2 * sizeof(T) + NPHYS * NPTS * sizeof(T) + 8 * (kNT / 64) * sizeof(double);
   static_assert(MZ % PP == 0 && PP % 2 == 0, "chunk rows must divide Mz and pair up");
 };
 
@@ -99,7 +103,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   __shared__ C rootP[PP];
   __shared__ C zb[Cfg::ZB];
   __shared__ C mid[Cfg::MID];
-  __shared__ T phys[NPHYS][Cfg::NPT];
+  __shared__ T phys[NPHYS][Cfg::NPTS];
   __shared__ double red[8][kNT / 64];
 
   const int tid = threadIdx.x;
@@ -172,7 +176,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
         const int fi = b / L, nx = b - fi * L;
         zb[(fi * PP + q) * Cfg::ZP + nx] = v;
       };
-      fft2pass<T, PP, +1, NF * L, kNT>(mid, rootP, load, store);
+      fft2pass<T, PP, +1, NF * L, kNT, true>(mid, rootP, load, store);
     };
     // ---- x inverse of NF fields held in zb, rows paired (q, q + PH) -------
     auto xinv = [&](auto nf_tag, bool dx, auto action) {
@@ -201,8 +205,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       };
       auto store = [&](int b, int n, C v) {
         const int fi = b / PH, qp = b - fi * PH;
-        action(fi, qp * MX + n, v.x);
-        action(fi, (qp + PH) * MX + n, v.y);
+        action(fi, qp * Cfg::MXP + n, v.x);
+        action(fi, (qp + PH) * Cfg::MXP + n, v.y);
       };
       fft2pass<T, MX, +1, NF * PH, kNT>(mid, rootX, load, store);
     };
@@ -249,7 +253,9 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       if (want_stats) s_grad += double(val) * double(val);
     });
     __syncthreads();
-    for (int p = tid; p < Cfg::NPT; p += kNT) {
+    for (int pl = tid; pl < Cfg::NPT; pl += kNT) {
+      const int q = pl / MX;
+      const int p = q * Cfg::MXP + (pl - q * MX);
       const T u = phys[PU][p], v = phys[PV][p], w = phys[PW][p], vy = phys[PVY][p];
       phys[PNV][p] += v * vy;
       s_uv += double(u) * double(v);
@@ -266,7 +272,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     {
       auto load = [&](int b, int n) -> C {
         const int f = b / PH, qp = b - f * PH;
-        return C{phys[PNU + f][qp * MX + n], phys[PNU + f][(qp + PH) * MX + n]};
+        return C{phys[PNU + f][qp * Cfg::MXP + n], phys[PNU + f][(qp + PH) * Cfg::MXP + n]};
       };
       auto store = [&](int b, int k, C v) {
         if (k < L) zb[b * Cfg::FP + k] = v;
@@ -288,8 +294,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
         return C{T(0.5) * (zk.y - zm.y), T(-0.5) * (zk.x - zm.x)};
       };
       // Y is written to zb after pass 1 has consumed it (pass 2 reads only mid)
-      auto storeY = [&](int b, int k, C v) { zb[b * PP + k] = v; };
-      fft2pass<T, PP, -1, 3 * L, kNT>(mid, rootP, load, storeY);
+      auto storeY = [&](int b, int k, C v) { zb[b * Cfg::PPP + k] = v; };
+      fft2pass<T, PP, -1, 3 * L, kNT, true>(mid, rootP, load, storeY);
     }
     __syncthreads();
 #pragma unroll
@@ -302,7 +308,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
         const int nz = iz < P ? iz : iz - NZ;
         const int kk = ((nz % PP) + PP) % PP;
         const int t = (((r * nz) % MZ) + MZ) % MZ;
-        acc[k] = cadd(acc[k], cmul(zb[(f * L + nx) * PP + kk], rootZ[t]));
+        acc[k] = cadd(acc[k], cmul(zb[(f * L + nx) * Cfg::PPP + kk], rootZ[t]));
       }
     }
     __syncthreads();
