@@ -124,9 +124,37 @@ def cpu_baseline(w, name):
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": members * steps / dt, "unit": "member-steps/s", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model,
             "sample": f"{members} members x {steps} steps of {name} (numpy FP64, operators prebuilt)"}
+
+
+def serial_gpu(w, precision, stream, steps=50):
+    """One member at a time on the GPU (the paper's serial-versus-vectorized
+    comparison): member-steps/s of a one-member ensemble."""
+    from paper_2306_12739_amd import dns, inputs
+    import torch
+    one = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], 1, w["dt"])
+    one.set_stream(stream)
+    one.set_precision(precision)
+    one.set_option(dns.OPT_GRAPH, 1)
+    st = inputs.random_state(w["flow"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], 1, w["amplitude"],
+                             w["seed"], spectrum=w["spectrum"])
+    one.set_state(*st)
+    one.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    one.close()
+    return steps / dt
 
 
 def main():
@@ -148,8 +176,9 @@ def main():
     stream = torch.cuda.Stream()
     ens = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], E, w["dt"])
     ens.set_stream(stream)
-    ens.set_precision({"fp64": dns.PREC_FP64, "mixed": dns.PREC_MIXED_FP32,
-                       "3xbf16": dns.PREC_MIXED_3XBF16}[args.precision])
+    ens_precision = {"fp64": dns.PREC_FP64, "mixed": dns.PREC_MIXED_FP32,
+                     "3xbf16": dns.PREC_MIXED_3XBF16}[args.precision]
+    ens.set_precision(ens_precision)
     ens.set_option(dns.OPT_GRAPH, 0 if args.no_graph else 1)
     ens.set_state(*inputs.workload_state(name, ensemble=E))
     tuning = None if args.no_tune else ens.tune()
@@ -173,6 +202,7 @@ def main():
         print(f"warning: {int(s['failed'].sum())} members non-finite", file=sys.stderr)
 
     plane_ms, mode_ms = ens.kernel_times(args.kernel_reps)
+    serial = serial_gpu(w, ens_precision, stream)
     if args.copy_calibration:
         # reference kernel of known traffic: reads and writes exactly 256 MiB
         with torch.cuda.stream(stream):
@@ -223,6 +253,7 @@ def main():
         "grid_point_steps_per_s_nominal": value * w["Nx"] * w["Ny"] * w["Nz"],
         "wall_s": wall,
         "kernels": per_kernel,
+        "serial_gpu_member_steps_per_s": serial,
         "tuning": tuning,
         "roofline": roof,
         "cpu_baseline": cpu,

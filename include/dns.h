@@ -113,6 +113,14 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  otherwise); applies to the current precision   */
 #define DNS_OPT_MODE_TILE 6   /* value: members per workgroup of the per-mode kernel,
                                  1, 2, 4 or 8, fitting 160 KB of LDS           */
+#define DNS_OPT_CHAINS 7      /* value: 1..DNS_MAX_CHAINS (<= ensemble): the members
+                                 are advanced in this many contiguous chains, each
+                                 on a stream of its own forked from and joined
+                                 into the handle's stream, so that one chain's
+                                 advection kernel overlaps another's per-mode
+                                 kernel.  Results do not depend on it.  Default:
+                                 2 for ensembles of 8 or more members, else 1. */
+#define DNS_MAX_CHAINS 4
 
 #define DNS_PREC_FP64 0        /* every stage in FP64                               */
 #define DNS_PREC_MIXED_FP32 1  /* x-z FFTs and advection products in FP32, FP32

@@ -62,6 +62,11 @@ struct dns_handle {
   size_t staging_bytes = 0;
   int ET = 1, ntiles = 1;
   int plane_var[2] = {0, 0};  // plane-kernel variant per precision (FP64, mixed)
+  // member chains advanced concurrently within a step
+  int nchain = 1;
+  std::vector<hipStream_t> chain_stream;
+  std::vector<hipEvent_t> chain_join;
+  hipEvent_t chain_fork = nullptr;
   // progress
   long long steps = 0, samples = 0;
   bool vel_fresh = false;
@@ -124,6 +129,14 @@ void free_all(dns_handle* h) {
   for (hipEvent_t e : h->join)
     if (e) hipEventDestroy(e);
   h->join.clear();
+  for (hipStream_t st : h->chain_stream)
+    if (st) hipStreamDestroy(st);
+  h->chain_stream.clear();
+  for (hipEvent_t e : h->chain_join)
+    if (e) hipEventDestroy(e);
+  h->chain_join.clear();
+  if (h->chain_fork) hipEventDestroy(h->chain_fork);
+  h->chain_fork = nullptr;
   if (h->fork) hipEventDestroy(h->fork);
   h->fork = nullptr;
   void* bufs[] = {h->v, h->eta, h->U, h->W, h->hF, h->hG, h->hEU, h->hEW, h->vel, h->nl,
@@ -151,8 +164,11 @@ int ensure_staging(dns_handle* h, size_t bytes) {
   return DNS_OK;
 }
 
-ModeArgs mode_args(dns_handle* h, int stage) {
+ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   ModeArgs a{};
+  if (ec < 0) ec = h->E;
+  a.e0 = e0;
+  a.ec = ec;
   const int hi = stage == 0 ? 0 : 1;
   const double hval = stage == 0 ? 0.5 : 1.0;
   a.v = h->v;
@@ -197,7 +213,7 @@ ModeArgs mode_args(dns_handle* h, int stage) {
   a.NZ = h->NZ;
   a.G = h->G;
   a.ET = h->ET;
-  a.ntiles = h->ntiles;
+  a.ntiles = (ec + h->ET - 1) / h->ET;
   a.kxs = h->kxs;
   a.kzs = h->kzs;
   a.hdt = hval * h->dt;
@@ -209,8 +225,10 @@ ModeArgs mode_args(dns_handle* h, int stage) {
   return a;
 }
 
-PlaneArgs plane_args(dns_handle* h, bool sums) {
+PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1) {
   PlaneArgs a{};
+  a.e0 = e0;
+  a.ec = ec < 0 ? h->E : ec;
   a.vel = h->vel;
   a.nl = h->nl;
   a.means = h->means;
@@ -223,9 +241,9 @@ PlaneArgs plane_args(dns_handle* h, bool sums) {
   return a;
 }
 
-hipError_t plane_launch(dns_handle* h, bool sums) {
+hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr) {
   return launch_plane(h->precision, h->Nx, h->Nz, h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1],
-                      plane_args(h, sums), h->stream);
+                      plane_args(h, sums, e0, ec), st ? st : h->stream);
 }
 
 // Members per mode-kernel workgroup: 1, 2, 4 or 8, at most the ensemble size
@@ -244,8 +262,10 @@ void set_mode_tile(dns_handle* h, int et) {
   mode_lds_geometry(h->My, et, &h->CRP, &h->SR, &h->TR);
 }
 
-StatsArgs stats_args(dns_handle* h) {
+StatsArgs stats_args(dns_handle* h, int e0 = 0, int ec = -1) {
   StatsArgs a{};
+  a.e0 = e0;
+  a.ec = ec < 0 ? h->E : ec;
   a.psum = h->psum;
   a.means = h->means;
   a.U = h->U;
@@ -273,11 +293,52 @@ int refresh_velocities(dns_handle* h) {
 }
 
 // Enqueue one time step; requires the velocity buffer to hold the state's velocities.
-int enqueue_step(dns_handle* h) {
+void invalidate_graph(dns_handle* h);
+
+// Advance the members in n contiguous chains (streams and events made on first use).
+int set_chains(dns_handle* h, int n) {
+  if (n < 1 || n > DNS_MAX_CHAINS || n > h->E)
+    return fail(h, DNS_E_INVALID, "member chains must be 1..DNS_MAX_CHAINS and at most the ensemble size");
+  while (int(h->chain_stream.size()) < n) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    HIP_OR_FAIL(h, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    h->chain_stream.push_back(st);
+    HIP_OR_FAIL(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    h->chain_join.push_back(ev);
+  }
+  if (!h->chain_fork) HIP_OR_FAIL(h, hipEventCreateWithFlags(&h->chain_fork, hipEventDisableTiming));
+  h->nchain = n;
+  invalidate_graph(h);
+  return DNS_OK;
+}
+
+// One step of members [e0, e0 + ec) on stream st.
+int enqueue_members(dns_handle* h, int e0, int ec, hipStream_t st) {
   for (int s = 0; s < 3; ++s) {
-    HIP_OR_FAIL(h, plane_launch(h, s == 0));
-    if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h), h->stats_on ? 1 : 0, h->stream));
-    HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s), h->stream));
+    HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st));
+    if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h, e0, ec), h->stats_on ? 1 : 0, st));
+    HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s, e0, ec), st));
+  }
+  return DNS_OK;
+}
+
+// Enqueue one time step; requires the velocity buffer to hold the state's
+// velocities.  With several member chains, each chain's kernels run on a stream
+// of its own (forked from and joined back into h->stream), so the advection
+// kernel of one chain overlaps the per-mode kernel of another.
+int enqueue_step(dns_handle* h) {
+  const int nc = h->nchain;
+  if (nc <= 1) return enqueue_members(h, 0, h->E, h->stream);
+  HIP_OR_FAIL(h, hipEventRecord(h->chain_fork, h->stream));
+  for (int c = 0; c < nc; ++c) {
+    const int e0 = int((long long)h->E * c / nc), e1 = int((long long)h->E * (c + 1) / nc);
+    hipStream_t st = h->chain_stream[c];
+    HIP_OR_FAIL(h, hipStreamWaitEvent(st, h->chain_fork, 0));
+    const int rc = enqueue_members(h, e0, e1 - e0, st);
+    if (rc) return rc;
+    HIP_OR_FAIL(h, hipEventRecord(h->chain_join[c], st));
+    HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->chain_join[c], 0));
   }
   return DNS_OK;
 }
@@ -568,6 +629,8 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
     return fail_free(DNS_E_HIP, "hipStreamCreate");
   h->stream = h->own_stream;
+  // two member chains overlap the advection and per-mode kernels of a step
+  if (set_chains(h, h->E >= 8 ? 2 : 1) != DNS_OK) return fail_free(DNS_E_HIP, "creating chain streams");
 
   auto up = [&](double* dst, const std::vector<double>& src) {
     return hipMemcpy(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);
@@ -673,7 +736,7 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out) {
 int dns_set_option(dns_handle* h, int key, long long value) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
   ORDER_AFTER_PARENT(h);
-  if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS)) {
+  if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS || key == DNS_OPT_CHAINS)) {
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     for (dns_handle* sh : h->sub) {
       const int rc = dns_set_option(sh, key, value);
@@ -716,6 +779,11 @@ int dns_set_option(dns_handle* h, int key, long long value) {
         }
       return fail(h, DNS_E_UNSUPPORTED, "no plane-kernel variant with that many chunk rows");
     }
+    case DNS_OPT_CHAINS:
+      if (value < 1 || value > DNS_MAX_CHAINS || value > h->E)
+        return fail(h, DNS_E_INVALID, "member chains must be 1..DNS_MAX_CHAINS and at most the ensemble size");
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      return set_chains(h, int(value));
     case DNS_OPT_MODE_TILE:
       if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
       if (!mode_tile_ok(h, int(value)))

@@ -32,6 +32,7 @@ struct PlaneArgs {
   double* means;
   double* psum;   // nullptr: skip statistics sums
   int My, K, E;
+  int e0, ec;       // members [e0, e0 + ec) of this launch
   double kxs, kzs;  // 2 pi / Lx, 2 pi / Lz
 };
 
@@ -76,6 +77,7 @@ struct ModeArgs {
   unsigned long long* divmax;  // [E] (bit pattern of a non-negative double)
   // sizes and parameters
   int My, N, K, E, L, P, NZ, G, ET, ntiles;
+  int e0, ec;           // members [e0, e0 + ec) of this launch (ntiles covers ec)
   int CRP, SR, TR;      // LDS geometry (mode_lds_geometry)
   double kxs, kzs, hdt, Ubot, Utop, Qtarget;
   int stage;      // 0, 1, 2: sub-step index; -1: velocities of the state only
@@ -132,6 +134,7 @@ struct StatsArgs {
   double* inst;          // [NDI][E] instantaneous per-member diagnostics
   int* failed;           // [E] sticky non-finite flag
   int My, E;
+  int e0, ec;            // members [e0, e0 + ec) of this launch
   double Re, Uw, poiseuille, Qtarget;
 };
 enum ProfileAcc { PA_U = 0, PA_W, PA_U2, PA_W2, PA_UU, PA_VV, PA_WW, PA_UV, NPA };

@@ -73,8 +73,8 @@ int grid_for(size_t n) {
 // (fixed summation order), wall shear, power input, finiteness, and the
 // optional time accumulation of the plane profiles.
 __global__ void stats_kernel(StatsArgs a, int accumulate) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= a.E) return;
+  const int e = a.e0 + int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= a.e0 + a.ec) return;
   const int My = a.My, E = a.E;
   double en = 0.0, ds = 0.0, q = 0.0, dlo = 0.0, dhi = 0.0;
   for (int j = 0; j < My; ++j) {
@@ -149,7 +149,7 @@ hipError_t launch_profile_from_device(const double* src, double* dst, int E0, in
 }
 
 hipError_t launch_stats(const StatsArgs& a, int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(stats_kernel, dim3((a.E + 63) / 64), dim3(64), 0, s, a, accumulate);
+  hipLaunchKernelGGL(stats_kernel, dim3((a.ec + 63) / 64), dim3(64), 0, s, a, accumulate);
   return hipGetLastError();
 }
 

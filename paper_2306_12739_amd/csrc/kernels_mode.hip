@@ -190,10 +190,11 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   const size_t KE = size_t(K) * E;
   const size_t FS = 2 * size_t(My) * KE;  // stage-buffer field stride (VT units)
 
-  auto col_member = [&](int c) { return tile * ET + (c - (c / ET) * ET); };
+  const int m0 = a.e0, mend = a.e0 + a.ec;  // members of this launch
+  auto col_member = [&](int c) { return m0 + tile * ET + (c - (c / ET) * ET); };
   auto col_valid = [&](int c) {
     const int sl = c / ET;
-    return tile * ET + (c - sl * ET) < E && (sl == 0 || az > 0);
+    return m0 + tile * ET + (c - sl * ET) < mend && (sl == 0 || az > 0);
   };
   auto col_mode = [&](int c) { return nx * NZ + (c / ET == 0 ? az : NZ - az); };
   auto col_kz = [&](int c) { return (c / ET == 0 ? 1.0 : -1.0) * a.kzs * az; };
@@ -518,8 +519,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   if (s >= 0) {
     // plane means (FH halves)
     for (int q = tid; q < Fe * NM; q += kNT) {
-      const int k = q / NM, el = q - k * NM, e = tile * ET + el;
-      if (e >= E) continue;
+      const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+      if (e >= mend) continue;
       const int j2 = My - 1 - k;
 #pragma unroll
       for (int comp = 0; comp < 2; ++comp) {
@@ -543,8 +544,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     });
     __syncthreads();
     for (int q = tid; q < N * NM; q += kNT) {
-      const int hr = q / NM, el = q - hr * NM, e = tile * ET + el;
-      if (e >= E) continue;
+      const int hr = q / NM, el = q - hr * NM, e = m0 + tile * ET + el;
+      if (e >= mend) continue;
       const bool even = hr < He;
       const int kk = even ? hr : hr - He;
       const int rowF = even ? He + kk : 2 * He + Ho + kk;
@@ -601,7 +602,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     __syncthreads();
     // bulk flux of the provisional U (even half only) and gamma per member
     if (tid < NM) {
-      const int el = tid, e = tile * ET + el;
+      const int el = tid, e = m0 + tile * ET + el;
       double gam = 0.0;
       if (a.poiseuille) {
         double qa = 0.0, wg = 0.0;
@@ -612,7 +613,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
         gam = (a.Qtarget - qa) / wg;
       }
       gam_s[el] = gam;
-      if (e < E) a.gamma[e] = gam;
+      if (e < mend) a.gamma[e] = gam;
     }
     __syncthreads();
     // gamma response is even (the green function is symmetric)
@@ -623,8 +624,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     __syncthreads();
     if (s == 2) {
       for (int q = tid; q < Fe * NM; q += kNT) {
-        const int k = q / NM, el = q - k * NM, e = tile * ET + el;
-        if (e >= E) continue;
+        const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+        if (e >= mend) continue;
         const double ue = T[k * CRP + 2 * el], we = T[k * CRP + 2 * el + 1];
         if (k < Fo) {
           const double uo = T[(Fe + k) * CRP + 2 * el], wo = T[(Fe + k) * CRP + 2 * el + 1];
@@ -646,8 +647,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     }
   } else {
     for (int q = tid; q < Fe * NM; q += kNT) {
-      const int k = q / NM, el = q - k * NM, e = tile * ET + el;
-      if (e >= E) continue;
+      const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+      if (e >= mend) continue;
       const size_t j1 = size_t(k) * E + e, j2 = size_t(My - 1 - k) * E + e;
       if (k < Fo) {
         T[k * CRP + 2 * el] = 0.5 * (a.U[j1] + a.U[j2]);
@@ -670,8 +671,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   });
   __syncthreads();
   for (int q = tid; q < Fe * NM; q += kNT) {
-    const int k = q / NM, el = q - k * NM, e = tile * ET + el;
-    if (e >= E) continue;
+    const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+    if (e >= mend) continue;
     const bool pair = k < Fo;
     for (int side = 0; side < (pair ? 2 : 1); ++side) {
       const double sg = side == 0 ? 1.0 : -1.0;

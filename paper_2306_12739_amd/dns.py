@@ -32,6 +32,7 @@ OPT_GRAPH = 3
 OPT_STATS = 4
 OPT_PLANE_ROWS = 5
 OPT_MODE_TILE = 6
+OPT_CHAINS = 7
 
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1

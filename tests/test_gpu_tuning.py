@@ -112,3 +112,32 @@ def test_tune_and_cache(tmp_path):
     for x, y in zip(a, b):  # same tile shapes: same bits
         assert np.array_equal(x, y)
     assert len(cache.read_text().strip().splitlines()) == 1
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_member_chains_bitwise_identical(graph):
+    say(f"case: member chains 1, 2, 3, 4 on 32x49x32, E=11, 3 steps, graph={graph}")
+    E = 11
+    st = inputs.random_state(0, 1.75 * np.pi, 1.2 * np.pi, 32, 49, 32, E, 0.2, 8, spectrum="k2")
+    out = []
+    for nc in (1, 2, 3, 4):
+        ens = dns.Ensemble(0, 600.0, 1.75 * np.pi, 1.2 * np.pi, 32, 49, 32, E, 0.02)
+        ens.set_option(dns.OPT_CHAINS, nc)
+        ens.set_option(dns.OPT_GRAPH, graph)
+        ens.set_option(dns.OPT_STATS, 1)
+        ens.set_state(*st)
+        ens.step(3)
+        out.append((ens.get_state(), ens.stats()))
+        ens.close()
+    (ref, sref) = out[0]
+    for (other, so) in out[1:]:
+        for a, b in zip(ref, other):
+            assert np.array_equal(a, b)
+        for k in ("energy", "U", "urms", "gamma", "div_max"):
+            assert np.array_equal(sref[k], so[k]), k
+    with pytest.raises(dns.DnsError):
+        ens = dns.Ensemble(0, 600.0, 1.75 * np.pi, 1.2 * np.pi, 32, 49, 32, 2, 0.02)
+        try:
+            ens.set_option(dns.OPT_CHAINS, 3)
+        finally:
+            ens.close()
