@@ -191,13 +191,15 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   const size_t FS = 2 * size_t(My) * KE;  // stage-buffer field stride (VT units)
 
   const int m0 = a.e0, mend = a.e0 + a.ec;  // members of this launch
-  auto col_member = [&](int c) { return m0 + tile * ET + (c - (c / ET) * ET); };
+  // ET is a power of two: index arithmetic by shifts and masks
+  const int ets = __ffs(ET) - 1, cs = ets + 1;  // C = 2 ET = 1 << cs
+  auto col_member = [&](int c) { return m0 + tile * ET + (c & (ET - 1)); };
   auto col_valid = [&](int c) {
-    const int sl = c / ET;
+    const int sl = c >> ets;
     return m0 + tile * ET + (c - sl * ET) < mend && (sl == 0 || az > 0);
   };
-  auto col_mode = [&](int c) { return nx * NZ + (c / ET == 0 ? az : NZ - az); };
-  auto col_kz = [&](int c) { return (c / ET == 0 ? 1.0 : -1.0) * a.kzs * az; };
+  auto col_mode = [&](int c) { return nx * NZ + (c < ET ? az : NZ - az); };
+  auto col_kz = [&](int c) { return (c < ET ? 1.0 : -1.0) * a.kzs * az; };
   // stage-buffer element (node j, column c) in VT units
   auto sb = [&](int j, int c) { return 2 * ((size_t(j) * E + col_member(c)) * K + col_mode(c)); };
   // state element (interior node i in [0, N), column c)
@@ -229,7 +231,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     if (s >= 0) {
       // Q on every node (FH), -k^2 N_v and G on interior nodes (solve stacks)
       for (int q = tid; q < Fe * C; q += kNT) {
-        const int k = q / C, c = q - k * C;
+        const int k = q >> cs, c = q & (C - 1);
         if (!col_valid(c)) continue;
         const double kz = col_kz(c), k2 = kx * kx + kz * kz;
         const bool pair = k < Fo;
@@ -277,7 +279,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       __syncthreads();
       // RK3 combination on halves (history kept in half layout); v0, eta0 halves
       for (int q = tid; q < N * C; q += kNT) {
-        const int hr = q / C, c = q - hr * C;
+        const int hr = q >> cs, c = q & (C - 1);
         if (!col_valid(c)) continue;
         const bool even = hr < He;
         const int kk = even ? hr : hr - He;
@@ -353,7 +355,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
         // a per-node combination of two columns, so it acts on halves as is
         if (nx == 0 && az > 0) {
           for (int q = tid; q < My * ET; q += kNT) {
-            const int i = q / ET, c0 = q - i * ET, c1 = c0 + ET;
+            const int i = q >> ets, c0 = q & (ET - 1), c1 = c0 + ET;
 #pragma unroll
             for (int bsel = 0; bsel < 2; ++bsel) {
               double* B = bsel == 0 ? T : S;
@@ -370,7 +372,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
         }
         // state: interior node pairs (kk, N-1-kk) from FH rows 1 + kk, Fe + 1 + kk
         for (int q = tid; q < He * C; q += kNT) {
-          const int kk = q / C, c = q - kk * C;
+          const int kk = q >> cs, c = q & (C - 1);
           if (!col_valid(c)) continue;
           const int re = 1 + kk, ro = Fe + 1 + kk;
           const double ver = T[re * CRP + 2 * c], vei = T[re * CRP + 2 * c + 1];
@@ -405,7 +407,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     } else {
       // velocities of the stored state: v -> T (FH), eta -> S (FH)
       for (int q = tid; q < He * C; q += kNT) {
-        const int kk = q / C, c = q - kk * C;
+        const int kk = q >> cs, c = q & (C - 1);
         if (!col_valid(c)) continue;
         const size_t s1 = st(kk, c);
         const int re = 1 + kk, ro = Fe + 1 + kk;
@@ -438,7 +440,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     __syncthreads();
     double dmax = 0.0;
     for (int q = tid; q < Fe * C; q += kNT) {
-      const int k = q / C, c = q - k * C;
+      const int k = q >> cs, c = q & (C - 1);
       const double kz = col_kz(c), k2 = kx * kx + kz * kz;
       const double ik2 = k2 > 0.0 ? 1.0 / k2 : 0.0;
       const bool pair = k < Fo;
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     });
     __syncthreads();
     for (int q = tid; q < Fe * C; q += kNT) {
-      const int k = q / C, c = q - k * C;
+      const int k = q >> cs, c = q & (C - 1);
       if (!col_valid(c)) continue;
       write_pair(T, k, c, 3);
       write_pair(S2, k, c, 4);
@@ -505,7 +507,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
       if (tid < C && col_valid(tid)) {
         double mx = 0.0;
         for (int q = 0; q < kNT; ++q)
-          if ((q % C) == tid) mx = fmax(mx, red[q]);
+          if ((q & (C - 1)) == tid) mx = fmax(mx, red[q]);
         atomicMax(&a.divmax[col_member(tid)], (unsigned long long)__double_as_longlong(mx));
       }
     }
@@ -519,7 +521,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   if (s >= 0) {
     // plane means (FH halves)
     for (int q = tid; q < Fe * NM; q += kNT) {
-      const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+      const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
       if (e >= mend) continue;
       const int j2 = My - 1 - k;
 #pragma unroll
@@ -544,7 +546,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     });
     __syncthreads();
     for (int q = tid; q < N * NM; q += kNT) {
-      const int hr = q / NM, el = q - hr * NM, e = m0 + tile * ET + el;
+      const int hr = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
       if (e >= mend) continue;
       const bool even = hr < He;
       const int kk = even ? hr : hr - He;
@@ -588,7 +590,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     __syncthreads();
     // wall pair, lift on the interior halves
     for (int q = tid; q < Fe * NM; q += kNT) {
-      const int k = q / NM, el = q - k * NM;
+      const int k = q >> ets, el = q & (NM - 1);
       if (k == 0) {
         T[2 * el] = 0.5 * (a.Ubot + a.Utop);
         T[2 * el + 1] = 0.0;
@@ -618,13 +620,13 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     __syncthreads();
     // gamma response is even (the green function is symmetric)
     for (int q = tid; q < He * NM; q += kNT) {
-      const int kk = q / NM, el = q - kk * NM;
+      const int kk = q >> ets, el = q & (NM - 1);
       T[(1 + kk) * CRP + 2 * el] += gam_s[el] * a.green_h[kk];
     }
     __syncthreads();
     if (s == 2) {
       for (int q = tid; q < Fe * NM; q += kNT) {
-        const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+        const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
         if (e >= mend) continue;
         const double ue = T[k * CRP + 2 * el], we = T[k * CRP + 2 * el + 1];
         if (k < Fo) {
@@ -647,7 +649,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
     }
   } else {
     for (int q = tid; q < Fe * NM; q += kNT) {
-      const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+      const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
       if (e >= mend) continue;
       const size_t j1 = size_t(k) * E + e, j2 = size_t(My - 1 - k) * E + e;
       if (k < Fo) {
@@ -671,7 +673,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   });
   __syncthreads();
   for (int q = tid; q < Fe * NM; q += kNT) {
-    const int k = q / NM, el = q - k * NM, e = m0 + tile * ET + el;
+    const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
     if (e >= mend) continue;
     const bool pair = k < Fo;
     for (int side = 0; side < (pair ? 2 : 1); ++side) {
