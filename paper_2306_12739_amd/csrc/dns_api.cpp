@@ -629,6 +629,10 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
     return fail_free(DNS_E_HIP, "hipStreamCreate");
   h->stream = h->own_stream;
+  // every kernel a step uses is resolved now, so that no captured step holds a
+  // kernel's first launch
+  if (plane_preload(Nx) != hipSuccess || mode_preload() != hipSuccess || misc_preload() != hipSuccess)
+    return fail_free(DNS_E_HIP, "resolving kernels");
   // two member chains overlap the advection and per-mode kernels of a step
   if (set_chains(h, h->E >= 8 ? 2 : 1) != DNS_OK) return fail_free(DNS_E_HIP, "creating chain streams");
 

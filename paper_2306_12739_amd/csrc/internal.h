@@ -91,6 +91,10 @@ hipError_t launch_plane(int precision, int Nx, int Nz, int variant, const PlaneA
 int plane_variants(int precision, int Nx, int* rows);
 bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
+// Resolve kernels on the current device before any graph capture uses them.
+hipError_t plane_preload(int Nx);
+hipError_t mode_preload();
+hipError_t misc_preload();
 int mode_member_tile(int My, int E);
 void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR);
 

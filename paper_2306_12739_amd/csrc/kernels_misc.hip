@@ -148,6 +148,21 @@ hipError_t launch_profile_from_device(const double* src, double* dst, int E0, in
   return hipGetLastError();
 }
 
+// Resolve the statistics and layout kernels on the current device.
+hipError_t misc_preload() {
+  const void* fns[5] = {reinterpret_cast<const void*>(&stats_kernel),
+                        reinterpret_cast<const void*>(&state_to_device),
+                        reinterpret_cast<const void*>(&state_from_device),
+                        reinterpret_cast<const void*>(&profile_to_device),
+                        reinterpret_cast<const void*>(&profile_from_device)};
+  for (const void* fn : fns) {
+    hipFuncAttributes attr;
+    const hipError_t err = hipFuncGetAttributes(&attr, fn);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_stats(const StatsArgs& a, int accumulate, hipStream_t s) {
   hipLaunchKernelGGL(stats_kernel, dim3((a.ec + 63) / 64), dim3(64), 0, s, a, accumulate);
   return hipGetLastError();

@@ -725,6 +725,19 @@ int mode_member_tile(int My, int E) {
   return best;
 }
 
+// Resolve the per-mode kernel instantiations on the current device.
+hipError_t mode_preload() {
+  const void* fns[3] = {reinterpret_cast<const void*>(&mode_kernel<double, false>),
+                        reinterpret_cast<const void*>(&mode_kernel<float, false>),
+                        reinterpret_cast<const void*>(&mode_kernel<float, true>)};
+  for (const void* fn : fns) {
+    hipFuncAttributes attr;
+    const hipError_t err = hipFuncGetAttributes(&attr, fn);
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   const int nblk = a.G * a.ntiles;
   const size_t lds = size_t(2 * a.SR + a.TR) * a.CRP * sizeof(double);

@@ -405,6 +405,56 @@ hipError_t run_rows(int pp, const PlaneArgs& a, hipStream_t s) {
 }
 }  // namespace
 
+namespace {
+template <typename T, int L, int PP>
+const void* plane_fn_if_fits() {
+  if constexpr ((3 * L) % PP == 0) {
+    if constexpr (PlaneCfg<T, L, L, PP>::kLdsBytes <= 160 * 1024)
+      return reinterpret_cast<const void*>(&plane_kernel<T, T, L, L, PP>);
+  }
+  return nullptr;
+}
+
+template <typename T, int L>
+const void* plane_fn(int pp) {
+  switch (pp) {
+    case 8: return plane_fn_if_fits<T, L, 8>();
+    case 12: return plane_fn_if_fits<T, L, 12>();
+    case 16: return plane_fn_if_fits<T, L, 16>();
+    case 24: return plane_fn_if_fits<T, L, 24>();
+    case 32: return plane_fn_if_fits<T, L, 32>();
+    case 36: return plane_fn_if_fits<T, L, 36>();
+    case 48: return plane_fn_if_fits<T, L, 48>();
+  }
+  return nullptr;
+}
+}  // namespace
+
+// Resolve every built plane-kernel variant of grid Nx (both precisions) on the
+// current device, so that a later graph capture never holds a kernel's first
+// launch.
+hipError_t plane_preload(int Nx) {
+  for (int prec = 0; prec < 2; ++prec) {
+    int rows[3];
+    const int n = plane_variants(prec, Nx, rows);
+    for (int v = 0; v < n; ++v) {
+      const void* fn = nullptr;
+      if (prec == 0) {
+        fn = Nx == 16 ? plane_fn<double, 8>(rows[v]) : Nx == 32 ? plane_fn<double, 16>(rows[v])
+           : Nx == 48 ? plane_fn<double, 24>(rows[v]) : plane_fn<double, 32>(rows[v]);
+      } else {
+        fn = Nx == 16 ? plane_fn<float, 8>(rows[v]) : Nx == 32 ? plane_fn<float, 16>(rows[v])
+           : Nx == 48 ? plane_fn<float, 24>(rows[v]) : plane_fn<float, 32>(rows[v]);
+      }
+      if (!fn) return hipErrorInvalidValue;
+      hipFuncAttributes attr;
+      const hipError_t err = hipFuncGetAttributes(&attr, fn);
+      if (err != hipSuccess) return err;
+    }
+  }
+  return hipSuccess;
+}
+
 int plane_variants(int precision, int Nx, int* rows) {
   const int gi = grid_index(Nx);
   if (gi < 0) return 0;
