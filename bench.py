@@ -124,6 +124,17 @@ def cpu_baseline(w, name):
     t0 = time.perf_counter()
     sim.step(steps)
     dt = time.perf_counter() - t0
+    # the same sample on one host thread
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+        sim.set_state(*inputs.workload_state(name, ensemble=members))
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            sim.step(steps)
+            one = members * steps / (time.perf_counter() - t1)
+    except ImportError:
+        pass
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -131,7 +142,7 @@ def cpu_baseline(w, name):
     except OSError:
         pass
     return {"value": members * steps / dt, "unit": "member-steps/s", "cores": int(cores),
-            "kind": "oracle", "cpu_model": model,
+            "kind": "oracle", "cpu_model": model, "value_1_thread": one,
             "sample": f"{members} members x {steps} steps of {name} (numpy FP64, operators prebuilt)"}
 
 

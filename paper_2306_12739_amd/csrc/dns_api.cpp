@@ -225,10 +225,15 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   return a;
 }
 
-PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1) {
+// walls = false leaves out the two wall planes, whose advection terms and
+// plane means vanish exactly (no-slip: v = 0 and u, w uniform in x-z there);
+// their statistics sums are still needed, so a launch with sums keeps them.
+PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool walls = true) {
   PlaneArgs a{};
   a.e0 = e0;
   a.ec = ec < 0 ? h->E : ec;
+  a.j0 = walls ? 0 : 1;
+  a.nj = walls ? h->My : h->My - 2;
   a.vel = h->vel;
   a.nl = h->nl;
   a.means = h->means;
@@ -241,9 +246,10 @@ PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1) {
   return a;
 }
 
-hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr) {
+hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr,
+                        bool walls = true) {
   return launch_plane(h->precision, h->Nx, h->Nz, h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1],
-                      plane_args(h, sums, e0, ec), st ? st : h->stream);
+                      plane_args(h, sums, e0, ec, walls || sums), st ? st : h->stream);
 }
 
 // Members per mode-kernel workgroup: 1, 2, 4 or 8, at most the ensemble size
@@ -316,7 +322,9 @@ int set_chains(dns_handle* h, int n) {
 // One step of members [e0, e0 + ec) on stream st.
 int enqueue_members(dns_handle* h, int e0, int ec, hipStream_t st) {
   for (int s = 0; s < 3; ++s) {
-    HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st));
+    // the first sub-step writes the (zero) wall-plane terms that the later
+    // sub-steps of the step then reuse
+    HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st, s == 0));
     if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h, e0, ec), h->stats_on ? 1 : 0, st));
     HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s, e0, ec), st));
   }

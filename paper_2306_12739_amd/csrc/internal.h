@@ -33,6 +33,7 @@ struct PlaneArgs {
   double* psum;   // nullptr: skip statistics sums
   int My, K, E;
   int e0, ec;       // members [e0, e0 + ec) of this launch
+  int j0, nj;       // planes [j0, j0 + nj) of this launch
   double kxs, kzs;  // 2 pi / Lx, 2 pi / Lz
 };
 

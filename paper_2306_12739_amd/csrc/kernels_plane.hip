@@ -109,7 +109,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   const int tid = threadIdx.x;
   const int flat = xcd_logical(blockIdx.x, gridDim.x);
   const int E = a.E, K = a.K, My = a.My;
-  const int j = flat / a.ec, e = a.e0 + (flat - j * a.ec);
+  const int jl = flat / a.ec;
+  const int j = a.j0 + jl, e = a.e0 + (flat - jl * a.ec);
   const VT* vel = static_cast<const VT*>(a.vel);
   const bool want_stats = a.psum != nullptr;
   const T kxs = T(a.kxs), kzs = T(a.kzs);
@@ -363,7 +364,7 @@ namespace {
 
 template <typename T, typename VT, int L, int P, int PP>
 hipError_t run_plane(const PlaneArgs& a, hipStream_t s) {
-  const int nblk = a.My * a.ec;
+  const int nblk = a.nj * a.ec;
   hipLaunchKernelGGL((plane_kernel<T, VT, L, P, PP>), dim3(nblk), dim3(kNT), 0, s, a);
   return hipGetLastError();
 }
