@@ -15,7 +15,9 @@ ensemble DNS") step by step, in the paper's order and notation:
                      2/3-rule dealiasing).
 * ``operators``   -- pre-inverted Crank-Nicolson operators per (kx, kz) pair
                      (Sec. 3.2, Eqs. (CN1)-(CN4), Listings 1 and 3).
-* ``step``        -- one CN/RK3 time step of the whole ensemble (Sec. 3.1).
+* ``step``        -- one CN/RK3 time step of the whole ensemble (Sec. 3.1),
+                     with the paper's advective nonlinear term or, as an
+                     alternative discretization, its rotational form.
 * ``diagnostics`` -- energy, dissipation, power input, flux, one-point
                      statistics (Sec. 4, one-point statistics paragraph).
 * ``sno``         -- learned spin-up (not in the paper): channel form of a

@@ -39,6 +39,21 @@ def dissipation(sim, vel=None):
     return (tot @ sim.ccw) / (sim.Re * LY)
 
 
+def dissipation_vorticity(sim, vel=None):
+    """eps from the enstrophy: 1/(Re Ly) int dy <|omega|^2>_xz per member.
+
+    For a divergence-free field between no-slip walls (v = 0 and uniform u, w at
+    each wall) the volume integrals of |grad u|^2 and |omega|^2 coincide: their
+    difference is a divergence whose wall flux u_j d_j v vanishes."""
+    vel = sim.velocities(sim.v, sim.eta, sim.U, sim.W) if vel is None else vel
+    g = sim.grid
+    ox = vel["wy"] - 1j * g.KZ * vel["v"]
+    oy = 1j * g.KZ * vel["u"] - 1j * g.KX * vel["w"]
+    oz = 1j * g.KX * vel["v"] - vel["uy"]
+    tot = plane_sq(sim, ox) + plane_sq(sim, oy) + plane_sq(sim, oz)
+    return (tot @ sim.ccw) / (sim.Re * LY)
+
+
 def wall_shear(sim):
     """dU/dy at the lower and upper wall per member."""
     dU = sim.U @ sim.ops.D1.T

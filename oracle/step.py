@@ -6,6 +6,8 @@ F^0, 2F^1 - F^0, (F^0 + 4F^1 + F^2)/6, every sub-step restarting from the state
 at t) and Sec. 3.2 (pre-inverted operators, u/w recovery from v and eta, the
 mean profiles evaluated separately).  Ensemble members are independent
 realisations advanced together; here they are simply a leading array axis.
+advection="rotational" replaces the advective term u . grad u by omega x u
+(same F and G for fields the grid resolves; see nonlinear_rotational).
 
 State layout (also the host layout of the library's state I/O):
   v, eta : complex (E, Nx/2, Nz-1, Ny-2)  -- interior Chebyshev nodes j = 1..Ny-2
@@ -25,8 +27,12 @@ POISEUILLE = 1
 class OracleDNS:
     """Plain FP64 reference of the ensemble step (Sec. 3)."""
 
-    def __init__(self, flow, Re, Lx, Lz, Nx, Ny, Nz, ensemble, dt, Uw=1.0, flux=4.0 / 3.0):
+    def __init__(self, flow, Re, Lx, Lz, Nx, Ny, Nz, ensemble, dt, Uw=1.0, flux=4.0 / 3.0,
+                 advection="convective"):
         self.flow = COUETTE if flow in (0, "couette") else POISEUILLE
+        if advection not in ("convective", "rotational"):
+            raise ValueError("advection must be 'convective' or 'rotational'")
+        self.advection = advection
         self.Re, self.dt, self.E = float(Re), float(dt), int(ensemble)
         self.Uw = float(Uw)
         self.grid = SpectralGrid(Lx, Lz, Nx, Nz)
@@ -151,6 +157,42 @@ class OracleDNS:
             out_w[e] = g.to_spectral(Nw)
         return out_u, out_v, out_w, uv, wv
 
+    def nonlinear_rotational(self, vel):
+        """Rotational form N = omega x u on the 3/2 grid, forward-transformed and
+        truncated; the plane means <uv>, <wv> are those of the advective form.
+
+        The momentum equation (Sec. 2, Eq. (1)) may carry its advection term as
+        u . grad u = omega x u + grad(|u|^2 / 2), with the gradient absorbed into
+        the pressure.  The v-eta equations take only the curl and the curl of the
+        curl of N (F and G below), which annihilate gradients, so this form needs
+        u, v, w and the three vorticity components in physical space (6 inverse
+        transforms instead of 12):
+          omega_x = d_y w - i kz v,  omega_y = i kz u - i kx w,  omega_z = i kx v - d_y u,
+          N = (omega_y w - omega_z v, omega_z u - omega_x w, omega_x v - omega_y u).
+        """
+        g = self.grid
+        ikx = 1j * g.KX
+        ikz = 1j * g.KZ
+        E = vel["u"].shape[0]
+        out_u = np.zeros_like(vel["u"])
+        out_v = np.zeros_like(vel["u"])
+        out_w = np.zeros_like(vel["u"])
+        uv = np.zeros((E, self.My))
+        wv = np.zeros((E, self.My))
+        for e in range(E):
+            P = g.to_physical
+            uh, vh, wh = vel["u"][e], vel["v"][e], vel["w"][e]
+            u, v, w = P(uh), P(vh), P(wh)
+            ox = P(vel["wy"][e] - ikz * vh)
+            oy = P(ikz * uh - ikx * wh)
+            oz = P(ikx * vh - vel["uy"][e])
+            uv[e] = (u * v).mean(axis=(-2, -1))
+            wv[e] = (w * v).mean(axis=(-2, -1))
+            out_u[e] = g.to_spectral(oy * w - oz * v)
+            out_v[e] = g.to_spectral(oz * u - ox * w)
+            out_w[e] = g.to_spectral(ox * v - oy * u)
+        return out_u, out_v, out_w, uv, wv
+
     # ---- a5: right-hand sides of Eqs. (Dv), (eta), (U00), (W00) -----------------
     def rhs(self, Nu, Nv, Nw, uv, wv):
         """F, G (interior rows) with d_t Lap v = -F + ..., d_t eta = -G + ...;
@@ -199,7 +241,10 @@ class OracleDNS:
     # ---- a10: one full time step --------------------------------------------------
     def stage_terms(self, x):
         vel = self.velocities(*x)
-        Nu, Nv, Nw, uv, wv = self.nonlinear(vel)
+        if self.advection == "rotational":
+            Nu, Nv, Nw, uv, wv = self.nonlinear_rotational(vel)
+        else:
+            Nu, Nv, Nw, uv, wv = self.nonlinear(vel)
         return self.rhs(Nu, Nv, Nw, uv, wv)
 
     def step(self, nsteps=1):
