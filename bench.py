@@ -46,12 +46,15 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tile shapes instead of running the tuner first")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--advection", choices=["advective", "rotational"], default="advective",
+                    help="form of the nonlinear term for the headline run; the other form is "
+                         "timed briefly on the same ensemble and reported beside it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
-def kernel_model(w, E, precision):
+def kernel_model(w, E, precision, form="advective"):
     """Algorithmic bytes and flops of one launch of each hot kernel."""
     Nx, Ny, Nz = w["Nx"], w["Ny"], w["Nz"]
     L, P, NZ, My, N = Nx // 2, Nz // 2, Nz - 1, Ny, Ny - 2
@@ -61,10 +64,13 @@ def kernel_model(w, E, precision):
     cplx = 2 * vt
     # advection kernel: read u,v,w,uy,wy spectra, write Nu,Nv,Nw spectra, plane means
     plane_bytes = (5 + 3) * My * K * E * cplx + 2 * My * E * 8
-    # flops: complex FFT 5 n log2 n, real FFT 2.5 n log2 n (conventional counts)
-    zinv = 8 * L * 5 * Mz * np.log2(Mz)
-    xinv = 11 * Mz * 2.5 * Mx * np.log2(Mx)
-    prod = Mx * Mz * (3 * 5 + 2 * 2)
+    # flops: complex FFT 5 n log2 n, real FFT 2.5 n log2 n (conventional counts);
+    # advective form: 8 z- and 11 x-inverses, u.grad u and the means; rotational
+    # form: 6 and 6, omega x u and the means
+    nz_inv, nx_inv, pw = (6, 6, 9 + 4) if form == "rotational" else (8, 11, 3 * 5 + 2 * 2)
+    zinv = nz_inv * L * 5 * Mz * np.log2(Mz)
+    xinv = nx_inv * Mz * 2.5 * Mx * np.log2(Mx)
+    prod = Mx * Mz * pw
     xfwd = 3 * Mz * 2.5 * Mx * np.log2(Mx)
     zfwd = 3 * L * 5 * Mz * np.log2(Mz)
     plane_flops = (zinv + xinv + prod + xfwd + zfwd) * My * E
@@ -168,6 +174,19 @@ def serial_gpu(w, precision, stream, steps=50):
     return steps / dt
 
 
+def time_steps(ens, stream, warmup, steps):
+    import torch
+    ens.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    ens.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -191,6 +210,8 @@ def main():
                      "3xbf16": dns.PREC_MIXED_3XBF16}[args.precision]
     ens.set_precision(ens_precision)
     ens.set_option(dns.OPT_GRAPH, 0 if args.no_graph else 1)
+    forms = {"advective": dns.ADV_ADVECTIVE, "rotational": dns.ADV_ROTATIONAL}
+    ens.set_advection(forms[args.advection])
     ens.set_state(*inputs.workload_state(name, ensemble=E))
     tuning = None if args.no_tune else ens.tune()
 
@@ -213,6 +234,19 @@ def main():
         print(f"warning: {int(s['failed'].sum())} members non-finite", file=sys.stderr)
 
     plane_ms, mode_ms = ens.kernel_times(args.kernel_reps)
+    # the other advection form, briefly, on the same ensemble (tuned for itself)
+    other = "rotational" if args.advection == "advective" else "advective"
+    ens.set_advection(forms[other])
+    ens.set_state(*inputs.workload_state(name, ensemble=E))
+    if not args.no_tune:
+        ens.tune()
+    o_steps = max(20, args.steps // 4)
+    o_ms = time_steps(ens, stream, 10, o_steps)
+    o_plane_ms, _ = ens.kernel_times(args.kernel_reps)
+    o_model = kernel_model(w, E, args.precision, other)["plane"]
+    alternative = {"advection": other, "steps": o_steps, "ms_per_step": o_ms / o_steps,
+                   "value": E * o_steps / (o_ms / 1e3), "plane_ms": o_plane_ms,
+                   "plane_TFLOP/s": o_model[1] / (o_plane_ms * 1e-3) / 1e12}
     serial = serial_gpu(w, ens_precision, stream)
     if args.copy_calibration:
         # reference kernel of known traffic: reads and writes exactly 256 MiB
@@ -226,7 +260,7 @@ def main():
     ms_step = ms / args.steps
     value = E * args.steps / (ms / 1e3)
     gp_paper = (w["Nx"] - 1) * (w["Nz"] - 1) * (w["Ny"] - 2)
-    model = kernel_model(w, E, args.precision)
+    model = kernel_model(w, E, args.precision, args.advection)
     per_kernel = {}
     for k, t in (("plane", plane_ms), ("mode", mode_ms)):
         b, f = model[k]
@@ -241,7 +275,7 @@ def main():
         roof = {"bound": "hbm", "achieved": pk["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": pk["GB/s"] / HBM_PEAK_GBS}
     roof["kernel"] = dom
-    roof["traffic"] = measured_traffic(dom, name, args.precision)
+    roof["traffic"] = measured_traffic(dom, name, args.precision) if args.advection == "advective" else None
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, name)
     out = {
@@ -259,12 +293,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "flow": "poiseuille" if w["flow"] else "couette",
                    "Re": w["Re"], "grid": f"{w['Nx']}x{w['Ny']}x{w['Nz']}", "ensemble": E,
-                   "dt": w["dt"], "precision": args.precision, "graph": not args.no_graph},
+                   "dt": w["dt"], "precision": args.precision, "graph": not args.no_graph,
+                   "advection": args.advection},
         "grid_point_steps_per_s": value * gp_paper,
         "grid_point_steps_per_s_nominal": value * w["Nx"] * w["Ny"] * w["Nz"],
         "wall_s": wall,
         "kernels": per_kernel,
         "serial_gpu_member_steps_per_s": serial,
+        "other_advection_form": alternative,
         "tuning": tuning,
         "roofline": roof,
         "cpu_baseline": cpu,

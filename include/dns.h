@@ -120,7 +120,20 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  advection kernel overlaps another's per-mode
                                  kernel.  Results do not depend on it.  Default:
                                  2 for ensembles of 8 or more members, else 1. */
+#define DNS_OPT_ADVECTION 8   /* value: DNS_ADV_*, the form of the advection term  */
 #define DNS_MAX_CHAINS 4
+
+/* Advection forms.  The paper advances the momentum equation (Sec. 2) with the
+ * advective term u . grad u (Sec. 3.2).  Its rotational form omega x u differs
+ * from it by the gradient of |u|^2 / 2, which the curl operators of the v-eta
+ * equations remove, so both forms solve the same equations; discretely they
+ * agree exactly for fields whose squared velocity the Chebyshev grid resolves
+ * and differ by collocation error otherwise.  The rotational form needs 6
+ * inverse x-z transforms per plane instead of 11.  With it, the dissipation
+ * of dns_stats is the enstrophy form 1/(Re V) int |omega|^2 (equal to the
+ * gradient form between no-slip walls). */
+#define DNS_ADV_ADVECTIVE 0   /* u . grad u (the paper's form; default)          */
+#define DNS_ADV_ROTATIONAL 1  /* omega x u                                       */
 
 #define DNS_PREC_FP64 0        /* every stage in FP64                               */
 #define DNS_PREC_MIXED_FP32 1  /* x-z FFTs and advection products in FP32, FP32
@@ -174,7 +187,7 @@ int dns_step(dns_handle* h, int nsteps);
  * `ensemble` (per member) or Ny (profiles) are owned by the caller.
  * Volume averages use Clenshaw-Curtis weights over y and divide by Ly = 2.
  *   energy      E = 1/(2V) int |u|^2 (mean flow included)
- *   dissipation eps = 1/(Re V) int |grad u|^2
+ *   dissipation eps = 1/(Re V) int |grad u|^2 (|omega|^2 with DNS_ADV_ROTATIONAL)
  *   power       Couette Uw (U'(1) + U'(-1)) / (Re Ly); channel gamma Q / Ly
  *   flux        Q = int U dy;  gamma: pressure gradient of the last sub-step
  *   div_max     max over modes/nodes of |i kx u + dv/dy + i kz w|

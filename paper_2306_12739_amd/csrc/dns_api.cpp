@@ -62,6 +62,7 @@ struct dns_handle {
   size_t staging_bytes = 0;
   int ET = 1, ntiles = 1;
   int plane_var[2] = {0, 0};  // plane-kernel variant per precision (FP64, mixed)
+  int advection = DNS_ADV_ADVECTIVE;
   // member chains advanced concurrently within a step
   int nchain = 1;
   std::vector<hipStream_t> chain_stream;
@@ -225,9 +226,11 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   return a;
 }
 
-// walls = false leaves out the two wall planes, whose advection terms and
-// plane means vanish exactly (no-slip: v = 0 and u, w uniform in x-z there);
-// their statistics sums are still needed, so a launch with sums keeps them.
+// walls = false leaves out the two wall planes.  There, no-slip (v = 0 and u,
+// w uniform in x-z) makes the plane means and the terms N_u, N_w vanish
+// exactly in both advection forms; N_v at a wall (zero in the advective form,
+// -u du/dy in the rotational one) enters no interior equation.  Their
+// statistics sums are still needed, so a launch with sums keeps them.
 PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool walls = true) {
   PlaneArgs a{};
   a.e0 = e0;
@@ -248,7 +251,8 @@ PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool wal
 
 hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr,
                         bool walls = true) {
-  return launch_plane(h->precision, h->Nx, h->Nz, h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1],
+  return launch_plane(h->precision, h->advection, h->Nx, h->Nz,
+                      h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1],
                       plane_args(h, sums, e0, ec, walls || sums), st ? st : h->stream);
 }
 
@@ -322,8 +326,8 @@ int set_chains(dns_handle* h, int n) {
 // One step of members [e0, e0 + ec) on stream st.
 int enqueue_members(dns_handle* h, int e0, int ec, hipStream_t st) {
   for (int s = 0; s < 3; ++s) {
-    // the first sub-step writes the (zero) wall-plane terms that the later
-    // sub-steps of the step then reuse
+    // the first sub-step writes the wall-plane terms that the later sub-steps
+    // of the step then reuse (the solves read only their exact zeros)
     HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st, s == 0));
     if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h, e0, ec), h->stats_on ? 1 : 0, st));
     HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s, e0, ec), st));
@@ -748,7 +752,8 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out) {
 int dns_set_option(dns_handle* h, int key, long long value) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
   ORDER_AFTER_PARENT(h);
-  if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS || key == DNS_OPT_CHAINS)) {
+  if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS || key == DNS_OPT_CHAINS ||
+                       key == DNS_OPT_ADVECTION)) {
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     for (dns_handle* sh : h->sub) {
       const int rc = dns_set_option(sh, key, value);
@@ -796,6 +801,14 @@ int dns_set_option(dns_handle* h, int key, long long value) {
         return fail(h, DNS_E_INVALID, "member chains must be 1..DNS_MAX_CHAINS and at most the ensemble size");
       HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
       return set_chains(h, int(value));
+    case DNS_OPT_ADVECTION:
+      if (value != DNS_ADV_ADVECTIVE && value != DNS_ADV_ROTATIONAL)
+        return fail(h, DNS_E_INVALID, "unknown advection form");
+      if (value != h->advection) {
+        h->advection = int(value);
+        invalidate_graph(h);
+      }
+      return DNS_OK;
     case DNS_OPT_MODE_TILE:
       if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
       if (!mode_tile_ok(h, int(value)))
@@ -1148,20 +1161,22 @@ std::string tune_key(const dns_handle* h) {
          std::to_string(h->Nz) + " " + std::to_string(h->E);
 }
 
-// Last cache line "<precision> <Nx> <Ny> <Nz> <E> <plane_rows> <mode_members> <plane_ms> <mode_ms>"
-// whose key matches h.
+// Last cache line "<precision> <Nx> <Ny> <Nz> <E> <plane_rows> <mode_members> <plane_ms> <mode_ms>
+// [<advection form>]" whose key matches h (a line without the form is the advective form's).
 bool cache_lookup(const dns_handle* h, const char* path, dns_tuning* t) {
   if (!path) return false;
   std::FILE* f = std::fopen(path, "r");
   if (!f) return false;
   bool found = false;
-  int p, nx, ny, nz, e, rows, mem;
+  int p, nx, ny, nz, e, rows, mem, form;
   double pm, mm;
   char line[256];
   while (std::fgets(line, sizeof line, f)) {
-    if (std::sscanf(line, "%d %d %d %d %d %d %d %lf %lf", &p, &nx, &ny, &nz, &e, &rows, &mem, &pm, &mm) != 9)
-      continue;
-    if (p == h->precision && nx == h->Nx && ny == h->Ny && nz == h->Nz && e == h->E) {
+    form = DNS_ADV_ADVECTIVE;
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %d %lf %lf %d", &p, &nx, &ny, &nz, &e, &rows, &mem,
+                                &pm, &mm, &form);
+    if (got != 9 && got != 10) continue;
+    if (p == h->precision && nx == h->Nx && ny == h->Ny && nz == h->Nz && e == h->E && form == h->advection) {
       t->plane_rows = rows;
       t->mode_members = mem;
       t->plane_ms = pm;
@@ -1224,8 +1239,8 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
   if (cache) {
     std::FILE* f = std::fopen(cache, "a");
     if (!f) return fail(h, DNS_E_INVALID, std::string("cannot append to tune cache ") + cache);
-    std::fprintf(f, "%s %d %d %.6f %.6f\n", tune_key(h).c_str(), t.plane_rows, t.mode_members, t.plane_ms,
-                 t.mode_ms);
+    std::fprintf(f, "%s %d %d %.6f %.6f %d\n", tune_key(h).c_str(), t.plane_rows, t.mode_members, t.plane_ms,
+                 t.mode_ms, h->advection);
     std::fclose(f);
   }
   if (out) *out = t;

@@ -86,7 +86,9 @@ struct ModeArgs {
 };
 
 // Kernel launchers (kernels_*.hip).  Return hipSuccess or the launch error.
-hipError_t launch_plane(int precision, int Nx, int Nz, int variant, const PlaneArgs& a, hipStream_t s);
+// form 0: advective u . grad u; 1: rotational omega x u
+hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
+                        hipStream_t s);
 // Chunk-row counts of the plane-kernel variants built for (precision, Nx);
 // returns how many (<= 3), index 0 being the default.
 int plane_variants(int precision, int Nx, int* rows);

@@ -19,6 +19,14 @@
 //   XF x-FFT(Nu, Nv, Nw) -> ZF z-FFT of the chunk -> accumulate
 //      N_hat(nz) += e^{-2 pi i r nz / Mz} Y_r[nz mod PP] in registers.
 // Pairs of physical rows share one complex x transform (real + i imag).
+//
+// Rotational form (kRot): the advection term is taken as omega x u, which
+// differs from u . grad u by a gradient that the curl operators of the v-eta
+// equations annihilate (momentum equation, Sec. 2).  The vorticity
+//   omega = (dw/dy - i kz v, i kz u - i kx w, i kx v - du/dy)
+// is formed in the z fold, so a chunk needs 6 z- and 6 x-transforms:
+//   Z1 -> X1 phys u, v, w;  ZW z-iFFT(omega) -> XW phys omega;
+//   P  N = (oy w - oz v, oz u - ox w, ox v - oy u), plane sums.
 #include <type_traits>
 
 #include "fft.h"
@@ -93,7 +101,7 @@ struct PlaneCfg {
 
 }  // namespace
 
-template <typename T, typename VT, int L, int P, int PP>
+template <typename T, typename VT, int L, int P, int PP, bool kRot>
 __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   using C = cx<T>;
   using Cfg = PlaneCfg<T, L, P, PP>;
@@ -147,8 +155,10 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     // first, by the whole workgroup with consecutive threads on consecutive kz
     // (contiguous in the member-outer stage buffer), into zb[fi][n'][nx]; the
     // transform then reads LDS only and writes its output back to zb.
-    auto zinv = [&](auto nf_tag, int fbase, bool dz) {
+    // kind 0: fields fbase.. as stored; 1: times i kz; 2: the vorticity
+    auto zinv = [&](auto nf_tag, int fbase, auto kind_tag) {
       constexpr int NF = decltype(nf_tag)::value;
+      constexpr int kind = decltype(kind_tag)::value;
 #pragma unroll 1
       for (int it = tid; it < NF * L * PP; it += kNT) {
         const int np = it % PP;
@@ -162,8 +172,24 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
           if (n < P) nz = n;
           else if (n > MZ - P) nz = n - MZ;
           else continue;
-          C x = vel_at(fbase + fi, nx, nz >= 0 ? nz : nz + NZ);
-          if (dz) x = cmuli<1>(cscale(x, kzs * T(nz)));
+          const int izs = nz >= 0 ? nz : nz + NZ;
+          C x;
+          if constexpr (kind == 2) {
+            const T kz = kzs * T(nz), kx = kxs * T(nx);
+            if (fi == 0) {         // dw/dy - i kz v
+              const C vv = vel_at(1, nx, izs), wy = vel_at(4, nx, izs);
+              x = C{wy.x + kz * vv.y, wy.y - kz * vv.x};
+            } else if (fi == 1) {  // i (kz u - kx w)
+              const C uu = vel_at(0, nx, izs), ww = vel_at(2, nx, izs);
+              x = cmuli<1>(C{kz * uu.x - kx * ww.x, kz * uu.y - kx * ww.y});
+            } else {               // i kx v - du/dy
+              const C vv = vel_at(1, nx, izs), uy = vel_at(3, nx, izs);
+              x = C{-kx * vv.y - uy.x, kx * vv.x - uy.y};
+            }
+          } else {
+            x = vel_at(fbase + fi, nx, izs);
+            if constexpr (kind == 1) x = cmuli<1>(cscale(x, kzs * T(nz)));
+          }
           acc_f = cadd(acc_f, cmul(x, cconj(rootZ[(n * r) % MZ])));
         }
         zb[(fi * PP + np) * Cfg::ZP + nx] = acc_f;
@@ -213,11 +239,39 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     };
     std::integral_constant<int, 3> three;
     std::integral_constant<int, 2> two;
+    std::integral_constant<int, 0> plain;
+    std::integral_constant<int, 1> dz;
+    std::integral_constant<int, 2> vort;
 
-    zinv(three, 0, false);
+    zinv(three, 0, plain);
     __syncthreads();
     xinv(three, false, [&](int fi, int p, T val) { phys[PU + fi][p] = val; });
     __syncthreads();
+    if constexpr (kRot) {
+      zinv(three, 0, vort);
+      __syncthreads();
+      xinv(three, false, [&](int fi, int p, T val) {
+        phys[PNU + fi][p] = val;
+        if (want_stats) s_grad += double(val) * double(val);
+      });
+      __syncthreads();
+      for (int pl = tid; pl < Cfg::NPT; pl += kNT) {
+        const int q = pl / MX;
+        const int p = q * Cfg::MXP + (pl - q * MX);
+        const T u = phys[PU][p], v = phys[PV][p], w = phys[PW][p];
+        const T ox = phys[PNU][p], oy = phys[PNV][p], oz = phys[PNW][p];
+        phys[PNU][p] = oy * w - oz * v;
+        phys[PNV][p] = oz * u - ox * w;
+        phys[PNW][p] = ox * v - oy * u;
+        s_uv += double(u) * double(v);
+        s_wv += double(w) * double(v);
+        if (want_stats) {
+          s_uu += double(u) * double(u);
+          s_vv += double(v) * double(v);
+          s_ww += double(w) * double(w);
+        }
+      }
+    } else {
     xinv(three, true, [&](int fi, int p, T val) {
       const T u = phys[PU][p];
       if (fi == 0) {
@@ -231,7 +285,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       if (want_stats) s_grad += double(val) * double(val);
     });
     __syncthreads();
-    zinv(three, 0, true);
+    zinv(three, 0, dz);
     __syncthreads();
     xinv(three, false, [&](int fi, int p, T val) {
       const T w = phys[PW][p];
@@ -246,7 +300,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       if (want_stats) s_grad += double(val) * double(val);
     });
     __syncthreads();
-    zinv(two, 3, false);
+    zinv(two, 3, plain);
     __syncthreads();
     xinv(two, false, [&](int fi, int p, T val) {
       const T v = phys[PV][p];
@@ -268,6 +322,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
         s_grad += double(vy) * double(vy);
       }
     }
+    }  // advective form
     __syncthreads();
     // ---- forward x transform of (Nu, Nv, Nw); keep |kx| < L ----------------
     {
@@ -360,21 +415,6 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   }
 }
 
-namespace {
-
-template <typename T, typename VT, int L, int P, int PP>
-hipError_t run_plane(const PlaneArgs& a, hipStream_t s) {
-  const int nblk = a.nj * a.ec;
-  hipLaunchKernelGGL((plane_kernel<T, VT, L, P, PP>), dim3(nblk), dim3(kNT), 0, s, a);
-  return hipGetLastError();
-}
-
-}  // namespace
-
-bool plane_supported(int Nx, int Nz) {
-  return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64);
-}
-
 // Chunk-row variants (PP) built for each precision and grid; index 0 is the
 // default, the others are candidates for the tuner.  Every variant keeps the
 // workgroup's LDS within 160 KB.
@@ -384,73 +424,76 @@ constexpr int kVar32[4][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 
 int grid_index(int Nx) { return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : -1; }
 
 template <typename T, int L, int PP>
-hipError_t run_if_fits(const PlaneArgs& a, hipStream_t s) {
-  if constexpr ((3 * L) % PP == 0) {
-    if constexpr (PlaneCfg<T, L, L, PP>::kLdsBytes <= 160 * 1024) return run_plane<T, T, L, L, PP>(a, s);
+constexpr bool variant_built() {
+  constexpr int gi = L == 8 ? 0 : L == 16 ? 1 : L == 24 ? 2 : L == 32 ? 3 : -1;
+  if constexpr (gi < 0 || (3 * L) % PP != 0) {
+    return false;
+  } else {
+    if (PlaneCfg<T, L, L, PP>::kLdsBytes > 160 * 1024) return false;
+    for (int v = 0; v < 3; ++v)
+      if ((sizeof(T) == 8 ? kVar64 : kVar32)[gi][v] == PP) return true;
+    return false;
   }
-  return hipErrorInvalidValue;
 }
 
-template <typename T, int L>
-hipError_t run_rows(int pp, const PlaneArgs& a, hipStream_t s) {
+template <typename T, int L, int PP, bool Rot>
+const void* plane_fn_if_built() {
+  if constexpr (variant_built<T, L, PP>())
+    return reinterpret_cast<const void*>(&plane_kernel<T, T, L, L, PP, Rot>);
+  return nullptr;
+}
+
+template <typename T, int L, bool Rot>
+const void* plane_fn_rows(int pp) {
   switch (pp) {
-    case 8: return run_if_fits<T, L, 8>(a, s);
-    case 12: return run_if_fits<T, L, 12>(a, s);
-    case 16: return run_if_fits<T, L, 16>(a, s);
-    case 24: return run_if_fits<T, L, 24>(a, s);
-    case 32: return run_if_fits<T, L, 32>(a, s);
-    case 36: return run_if_fits<T, L, 36>(a, s);
-    case 48: return run_if_fits<T, L, 48>(a, s);
-  }
-  return hipErrorInvalidValue;
-}
-}  // namespace
-
-namespace {
-template <typename T, int L, int PP>
-const void* plane_fn_if_fits() {
-  if constexpr ((3 * L) % PP == 0) {
-    if constexpr (PlaneCfg<T, L, L, PP>::kLdsBytes <= 160 * 1024)
-      return reinterpret_cast<const void*>(&plane_kernel<T, T, L, L, PP>);
+    case 8: return plane_fn_if_built<T, L, 8, Rot>();
+    case 12: return plane_fn_if_built<T, L, 12, Rot>();
+    case 16: return plane_fn_if_built<T, L, 16, Rot>();
+    case 24: return plane_fn_if_built<T, L, 24, Rot>();
+    case 32: return plane_fn_if_built<T, L, 32, Rot>();
+    case 36: return plane_fn_if_built<T, L, 36, Rot>();
+    case 48: return plane_fn_if_built<T, L, 48, Rot>();
   }
   return nullptr;
 }
 
-template <typename T, int L>
-const void* plane_fn(int pp) {
-  switch (pp) {
-    case 8: return plane_fn_if_fits<T, L, 8>();
-    case 12: return plane_fn_if_fits<T, L, 12>();
-    case 16: return plane_fn_if_fits<T, L, 16>();
-    case 24: return plane_fn_if_fits<T, L, 24>();
-    case 32: return plane_fn_if_fits<T, L, 32>();
-    case 36: return plane_fn_if_fits<T, L, 36>();
-    case 48: return plane_fn_if_fits<T, L, 48>();
+template <typename T, bool Rot>
+const void* plane_fn_grid(int Nx, int pp) {
+  switch (Nx) {
+    case 16: return plane_fn_rows<T, 8, Rot>(pp);
+    case 32: return plane_fn_rows<T, 16, Rot>(pp);
+    case 48: return plane_fn_rows<T, 24, Rot>(pp);
+    case 64: return plane_fn_rows<T, 32, Rot>(pp);
   }
   return nullptr;
 }
+
+// The kernel of (precision, advection form, grid, chunk rows); nullptr if not built.
+const void* plane_fn(int precision, int form, int Nx, int pp) {
+  if (precision == 0) return form ? plane_fn_grid<double, true>(Nx, pp) : plane_fn_grid<double, false>(Nx, pp);
+  return form ? plane_fn_grid<float, true>(Nx, pp) : plane_fn_grid<float, false>(Nx, pp);
+}
 }  // namespace
 
-// Resolve every built plane-kernel variant of grid Nx (both precisions) on the
-// current device, so that a later graph capture never holds a kernel's first
-// launch.
+bool plane_supported(int Nx, int Nz) {
+  return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64);
+}
+
+// Resolve every built plane-kernel variant of grid Nx (both precisions, both
+// advection forms) on the current device, so that a later graph capture never
+// holds a kernel's first launch.
 hipError_t plane_preload(int Nx) {
   for (int prec = 0; prec < 2; ++prec) {
     int rows[3];
     const int n = plane_variants(prec, Nx, rows);
-    for (int v = 0; v < n; ++v) {
-      const void* fn = nullptr;
-      if (prec == 0) {
-        fn = Nx == 16 ? plane_fn<double, 8>(rows[v]) : Nx == 32 ? plane_fn<double, 16>(rows[v])
-           : Nx == 48 ? plane_fn<double, 24>(rows[v]) : plane_fn<double, 32>(rows[v]);
-      } else {
-        fn = Nx == 16 ? plane_fn<float, 8>(rows[v]) : Nx == 32 ? plane_fn<float, 16>(rows[v])
-           : Nx == 48 ? plane_fn<float, 24>(rows[v]) : plane_fn<float, 32>(rows[v]);
+    for (int form = 0; form < 2; ++form) {
+      for (int v = 0; v < n; ++v) {
+        const void* fn = plane_fn(prec, form, Nx, rows[v]);
+        if (!fn) return hipErrorInvalidValue;
+        hipFuncAttributes attr;
+        const hipError_t err = hipFuncGetAttributes(&attr, fn);
+        if (err != hipSuccess) return err;
       }
-      if (!fn) return hipErrorInvalidValue;
-      hipFuncAttributes attr;
-      const hipError_t err = hipFuncGetAttributes(&attr, fn);
-      if (err != hipSuccess) return err;
     }
   }
   return hipSuccess;
@@ -467,28 +510,18 @@ int plane_variants(int precision, int Nx, int* rows) {
 }
 
 // precision 0: FP64 storage and arithmetic; 1: FP32 storage and FFT arithmetic.
-hipError_t launch_plane(int precision, int Nx, int Nz, int variant, const PlaneArgs& a, hipStream_t s) {
-  if (!plane_supported(Nx, Nz)) return hipErrorInvalidValue;
+// form 0: advective u . grad u; 1: rotational omega x u.
+hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
+                        hipStream_t s) {
+  if (!plane_supported(Nx, Nz) || (form != 0 && form != 1)) return hipErrorInvalidValue;
   int rows[3];
   const int n = plane_variants(precision, Nx, rows);
   if (variant < 0 || variant >= n) return hipErrorInvalidValue;
-  const int pp = rows[variant];
-  if (precision == 0) {
-    switch (Nx) {
-      case 16: return run_rows<double, 8>(pp, a, s);
-      case 32: return run_rows<double, 16>(pp, a, s);
-      case 48: return run_rows<double, 24>(pp, a, s);
-      case 64: return run_rows<double, 32>(pp, a, s);
-    }
-  } else {
-    switch (Nx) {
-      case 16: return run_rows<float, 8>(pp, a, s);
-      case 32: return run_rows<float, 16>(pp, a, s);
-      case 48: return run_rows<float, 24>(pp, a, s);
-      case 64: return run_rows<float, 32>(pp, a, s);
-    }
-  }
-  return hipErrorInvalidValue;
+  const void* fn = plane_fn(precision, form, Nx, rows[variant]);
+  if (!fn) return hipErrorInvalidValue;
+  void* args[] = {const_cast<PlaneArgs*>(&a)};
+  const hipError_t err = hipLaunchKernel(fn, dim3(a.nj * a.ec), dim3(kNT), args, 0, s);
+  return err != hipSuccess ? err : hipGetLastError();
 }
 
 }  // namespace dns

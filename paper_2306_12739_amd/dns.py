@@ -33,6 +33,10 @@ OPT_STATS = 4
 OPT_PLANE_ROWS = 5
 OPT_MODE_TILE = 6
 OPT_CHAINS = 7
+OPT_ADVECTION = 8
+
+ADV_ADVECTIVE = 0
+ADV_ROTATIONAL = 1
 
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1
@@ -243,6 +247,9 @@ class Ensemble:
     def set_precision(self, prec):
         return self.set_option(OPT_PRECISION, prec)
 
+    def set_advection(self, form):
+        return self.set_option(OPT_ADVECTION, form)
+
     def set_stream(self, stream):
         """stream: a torch.cuda.Stream (or its integer handle)."""
         handle = getattr(stream, "cuda_stream", stream)
@@ -401,6 +408,9 @@ class GroupedEnsemble:
 
     def set_precision(self, prec):
         return self.set_option(OPT_PRECISION, prec)
+
+    def set_advection(self, form):
+        return self.set_option(OPT_ADVECTION, form)
 
     def set_stream(self, stream):
         handle = getattr(stream, "cuda_stream", stream)

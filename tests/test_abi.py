@@ -106,3 +106,11 @@ def test_ny_beyond_mode_lds_is_unsupported_without_gpu():
     geo = dns.Geometry(0, 1.75 * np.pi, 1.2 * np.pi, 1.0, 0.0)
     assert lib.dns_create(ctypes.byref(geo), 400.0, 16, 253, 16, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_UNSUPPORTED
     assert b"Ny" in lib.dns_last_error(None)
+
+
+def test_binding_constants_match_the_header():
+    text = open(HEADERS[0]).read()
+    defs = dict(re.findall(r"#define DNS_((?:OPT|PREC|ADV)_[A-Z0-9_]+)\s+(-?\d+)", text))
+    assert {"OPT_ADVECTION", "ADV_ADVECTIVE", "ADV_ROTATIONAL"} <= set(defs)
+    for name, value in defs.items():
+        assert getattr(dns, name) == int(value), name
