@@ -149,6 +149,42 @@ def test_rotational_steps_track_advective_for_resolved_flow():
     assert np.all(np.isfinite(E0))
 
 
+def _forms_gap(Ny, Nx=8, Nz=8):
+    """Relative F and G gaps between the forms for an analytic (not polynomial)
+    flow sampled on Ny Chebyshev nodes."""
+    sim = oracle.OracleDNS(0, 400.0, 1.75 * np.pi, 1.2 * np.pi, Nx, Ny, Nz, 1, 0.01)
+    y = sim.y[1:-1]
+    L, NZ, N = Nx // 2, Nz - 1, Ny - 2
+    v = np.zeros((1, L, NZ, N), complex)
+    eta = np.zeros_like(v)
+    v[0, 1, 1] = 0.3 * (1 - y ** 2) ** 2 * np.cos(2 * y + 0.3)
+    v[0, 2, NZ - 1] = 0.2j * (1 - y ** 2) ** 2 * np.exp(y)
+    eta[0, 1, 1] = 0.4 * (1 - y ** 2) * np.sin(3 * y)
+    eta[0, 1, 2] = 0.1 * (1 - y ** 2) / (2 - y)
+    yy = sim.y
+    U = (yy + 0.1 * (1 - yy ** 2) * np.sin(2 * yy))[None]
+    W = (0.05 * (1 - yy ** 2) * np.cos(yy))[None]
+    sim.set_state(v, eta, U, W)
+    vel = sim.velocities(sim.v, sim.eta, sim.U, sim.W)
+    Fc, Gc, _, _ = sim.rhs(*sim.nonlinear(vel))
+    Fr, Gr, _, _ = sim.rhs(*sim.nonlinear_rotational(vel))
+    return rel(Fr, Fc), rel(Gr, Gc)
+
+
+def test_forms_converge_spectrally():
+    """The forms differ only by the collocation error of D1 on |u|^2 / 2, which
+    falls faster than any power of 1/Ny for an analytic flow."""
+    gaps = [_forms_gap(ny) for ny in (13, 17, 21, 25, 29)]
+    F = [g[0] for g in gaps]
+    assert all(g[1] < 1e-14 for g in gaps)
+    assert F[0] > 1e-3
+    for a, b in zip(F, F[1:]):
+        assert b < 1e-2 * a or b < 1e-13, F
+    assert F[-1] < 1e-12
+    # the rate itself steepens (super-geometric), unlike an algebraic error
+    assert F[1] / F[0] > F[3] / F[2]
+
+
 # ---- planted mistakes (on the CPU) must trip the pins above --------------------
 def _plant(monkeypatch, fn):
     orig = oracle.OracleDNS.nonlinear_rotational
