@@ -20,6 +20,9 @@ ensemble DNS") step by step, in the paper's order and notation:
                      alternative discretization, its rotational form.
 * ``diagnostics`` -- energy, dissipation, power input, flux, one-point
                      statistics (Sec. 4, one-point statistics paragraph).
+* ``s3t``         -- approximate S3T ensemble (Sec. 4): members sharing one
+                     streamwise-mean flow, quasi-linear perturbations,
+                     additive (Lap v, eta) forcing.
 * ``sno``         -- learned spin-up (not in the paper): channel form of a
                      state and back to an admissible state, a spectral neural
                      operator with its gradient, AdamW.
@@ -34,11 +37,12 @@ from .cheb import (nodes, diff_matrix, dirichlet_d2, clamped_matrices,
 from .spectral import SpectralGrid
 from .operators import ModeOperators, MeanOperators
 from .step import OracleDNS
+from .s3t import OracleS3T
 from . import diagnostics
 from . import sno
 
 __all__ = [
     "nodes", "diff_matrix", "dirichlet_d2", "clamped_matrices",
     "clenshaw_curtis_weights", "SpectralGrid", "ModeOperators",
-    "MeanOperators", "OracleDNS", "diagnostics", "sno",
+    "MeanOperators", "OracleDNS", "OracleS3T", "diagnostics", "sno",
 ]
