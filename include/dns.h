@@ -121,6 +121,26 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  kernel.  Results do not depend on it.  Default:
                                  2 for ensembles of 8 or more members, else 1. */
 #define DNS_OPT_ADVECTION 8   /* value: DNS_ADV_*, the form of the advection term  */
+#define DNS_OPT_SHARED_MEAN 9 /* value: 1 the members share one streamwise-mean flow
+                                 (approximate S3T ensemble, Sec. 4: the n_x = 0
+                                 modes of v and eta and the profiles U00, W00),
+                                 advanced by the member averages of the members'
+                                 forcing terms of those modes, i.e. by the mean's
+                                 own advection plus the perturbation Reynolds
+                                 stresses averaged over the members.  Turning it
+                                 on replaces each member's mean by the member
+                                 average (so does dns_set_state while it is on)
+                                 and sets DNS_OPT_CHAINS to 1 (larger values are
+                                 then rejected).  Default 0.                    */
+#define DNS_OPT_QUASILINEAR 10 /* value: 1 the advection of the perturbations
+                                 (n_x >= 1) is linearised about the streamwise
+                                 mean, U_m . grad u' + u' . grad U_m, while the
+                                 mean keeps the full advection including the
+                                 streamwise average of u' . grad u' (the second-
+                                 cumulant closure of S3T).  Advective form only
+                                 (DNS_E_INVALID with DNS_ADV_ROTATIONAL).  Fewer
+                                 plane-kernel chunk-row variants fit its LDS.
+                                 Default 0.                                     */
 #define DNS_MAX_CHAINS 4
 
 /* Advection forms.  The paper advances the momentum equation (Sec. 2) with the
@@ -171,6 +191,22 @@ typedef struct {
  * 0; W00 = 0) within 1e-12.  Clears the members' failure flags.
  * Errors: DNS_E_INVALID. */
 int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s);
+
+/* Additive forcing of the (Lap v, eta) equations of members [member0,
+ * member0+count): d(Lap v)/dt and d(eta)/dt gain f_lapv and f_eta, held
+ * constant over each step until replaced (Sec. 4: the stochastic forcing of an
+ * S3T ensemble is a mixture of eigenvectors of the diffusion operator acting
+ * on a (Lap v, eta) state; the caller draws the mixture for each step and
+ * calls this before the step).  Layout as dns_state_view's v_hat/eta_hat:
+ * [member][n_x][n_z FFT order][j 1..Ny-2] interleaved complex doubles, host or
+ * device memory (on_device), read during the call; a NULL field counts as
+ * zero.  Both NULL: forcing off (the default).  With DNS_OPT_SHARED_MEAN the
+ * n_x = 0 modes of the forcing are replaced by their member average.  The
+ * first call allocates two state-sized device buffers; later calls reuse
+ * them, so a captured step graph stays valid while the forcing changes.
+ * Errors: DNS_E_INVALID (member range). */
+int dns_set_forcing(dns_handle* h, int member0, int count, const double* f_lapv, const double* f_eta,
+                    int on_device);
 
 /* Copy members [member0, member0+count) into s (synchronises the stream). */
 int dns_get_state(dns_handle* h, int member0, int count, dns_state_view* s);

@@ -61,8 +61,14 @@ struct dns_handle {
   double* staging = nullptr;
   size_t staging_bytes = 0;
   int ET = 1, ntiles = 1;
-  int plane_var[2] = {0, 0};  // plane-kernel variant per precision (FP64, mixed)
+  int plane_var[2][kPlaneForms] = {};  // plane-kernel variant per precision (FP64, mixed) and form
   int advection = DNS_ADV_ADVECTIVE;
+  // shared-mean ensemble: one streamwise mean for all members, optionally
+  // quasi-linear perturbations, and an additive (Lap v, eta) forcing
+  bool shared_mean = false;
+  bool quasilinear = false;
+  bool forcing_on = false;
+  double *fv = nullptr, *feta = nullptr;
   // member chains advanced concurrently within a step
   int nchain = 1;
   std::vector<hipStream_t> chain_stream;
@@ -145,7 +151,7 @@ void free_all(dns_handle* h) {
                   h->D1intT_e, h->D1intT_o, h->D1cT_e, h->D1cT_o, h->D1T_e, h->D1T_o,
                   h->lift_h[0], h->lift_h[1], h->green_h[0], h->green_h[1], h->ccw_h,
                   h->D1, h->ccw, h->cheb_cinv, h->cheb_t,
-                  h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging};
+                  h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging, h->fv, h->feta};
   for (void* p : bufs)
     if (p) hipFree(p);
   for (int i = 0; i < 6; ++i) {
@@ -178,6 +184,8 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   a.W = h->W;
   a.hF = h->hF;
   a.hG = h->hG;
+  a.fv = h->forcing_on ? h->fv : nullptr;
+  a.feta = h->forcing_on ? h->feta : nullptr;
   a.hEU = h->hEU;
   a.hEW = h->hEW;
   a.vel = h->vel;
@@ -249,10 +257,13 @@ PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool wal
   return a;
 }
 
+// plane-kernel form: 0 advective, 1 rotational, 2 quasi-linear advective
+int plane_form(const dns_handle* h) { return h->quasilinear ? 2 : h->advection; }
+int& plane_var(dns_handle* h) { return h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1][plane_form(h)]; }
+
 hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr,
                         bool walls = true) {
-  return launch_plane(h->precision, h->advection, h->Nx, h->Nz,
-                      h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1],
+  return launch_plane(h->precision, plane_form(h), h->Nx, h->Nz, plane_var(h),
                       plane_args(h, sums, e0, ec, walls || sums), st ? st : h->stream);
 }
 
@@ -329,6 +340,9 @@ int enqueue_members(dns_handle* h, int e0, int ec, hipStream_t st) {
     // the first sub-step writes the wall-plane terms that the later sub-steps
     // of the step then reuse (the solves read only their exact zeros)
     HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st, s == 0));
+    if (h->shared_mean)  // one chain holds every member (set_chains)
+      HIP_OR_FAIL(h, launch_member_mean(h->precision == DNS_PREC_FP64 ? 0 : 1, h->nl, h->means, h->My, h->E,
+                                        h->K, h->NZ, st));
     if (s == 0) HIP_OR_FAIL(h, launch_stats(stats_args(h, e0, ec), h->stats_on ? 1 : 0, st));
     HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, s, e0, ec), st));
   }
@@ -753,7 +767,8 @@ int dns_set_option(dns_handle* h, int key, long long value) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
   ORDER_AFTER_PARENT(h);
   if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS || key == DNS_OPT_CHAINS ||
-                       key == DNS_OPT_ADVECTION)) {
+                       key == DNS_OPT_ADVECTION || key == DNS_OPT_SHARED_MEAN ||
+                       key == DNS_OPT_QUASILINEAR)) {
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     for (dns_handle* sh : h->sub) {
       const int rc = dns_set_option(sh, key, value);
@@ -787,10 +802,10 @@ int dns_set_option(dns_handle* h, int key, long long value) {
     case DNS_OPT_PLANE_ROWS: {
       if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
       int rows[3];
-      const int n = plane_variants(h->precision, h->Nx, rows);
+      const int n = plane_variants(h->precision, plane_form(h), h->Nx, rows);
       for (int v = 0; v < n; ++v)
         if (rows[v] == value) {
-          h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1] = v;
+          plane_var(h) = v;
           invalidate_graph(h);
           return DNS_OK;
         }
@@ -799,15 +814,45 @@ int dns_set_option(dns_handle* h, int key, long long value) {
     case DNS_OPT_CHAINS:
       if (value < 1 || value > DNS_MAX_CHAINS || value > h->E)
         return fail(h, DNS_E_INVALID, "member chains must be 1..DNS_MAX_CHAINS and at most the ensemble size");
+      if (value > 1 && h->shared_mean)
+        return fail(h, DNS_E_INVALID, "a shared-mean ensemble advances its members in one chain");
       HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
       return set_chains(h, int(value));
     case DNS_OPT_ADVECTION:
       if (value != DNS_ADV_ADVECTIVE && value != DNS_ADV_ROTATIONAL)
         return fail(h, DNS_E_INVALID, "unknown advection form");
+      if (value != DNS_ADV_ADVECTIVE && h->quasilinear)
+        return fail(h, DNS_E_INVALID, "the quasi-linear dynamics use the advective form");
       if (value != h->advection) {
         h->advection = int(value);
         invalidate_graph(h);
       }
+      return DNS_OK;
+    case DNS_OPT_SHARED_MEAN: {
+      if (value != 0 && value != 1) return fail(h, DNS_E_INVALID, "shared mean is 0 or 1");
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      if (value && h->nchain > 1) {
+        const int rc = set_chains(h, 1);
+        if (rc) return rc;
+      }
+      h->shared_mean = value != 0;
+      if (h->shared_mean) {
+        HIP_OR_FAIL(h, launch_share_columns(h->v, h->eta, h->U, h->W, h->E, h->N, h->NZ, h->My, h->stream));
+        if (h->fv)
+          HIP_OR_FAIL(h, launch_share_columns(h->fv, h->feta, nullptr, nullptr, h->E, h->N, h->NZ, h->My,
+                                              h->stream));
+        HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+        h->vel_fresh = false;
+      }
+      invalidate_graph(h);
+      return DNS_OK;
+    }
+    case DNS_OPT_QUASILINEAR:
+      if (value != 0 && value != 1) return fail(h, DNS_E_INVALID, "quasi-linear is 0 or 1");
+      if (value && h->advection != DNS_ADV_ADVECTIVE)
+        return fail(h, DNS_E_INVALID, "the quasi-linear dynamics use the advective form");
+      h->quasilinear = value != 0;
+      invalidate_graph(h);
       return DNS_OK;
     case DNS_OPT_MODE_TILE:
       if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
@@ -865,8 +910,60 @@ int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s
   HIP_OR_FAIL(h, launch_profile_to_device(st, h->U, member0, count, h->E, h->My, h->stream));
   HIP_OR_FAIL(h, launch_profile_to_device(st + nprof, h->W, member0, count, h->E, h->My, h->stream));
   HIP_OR_FAIL(h, hipMemsetAsync(h->failed + member0, 0, sizeof(int) * count, h->stream));
+  if (h->shared_mean)
+    HIP_OR_FAIL(h, launch_share_columns(h->v, h->eta, h->U, h->W, h->E, h->N, h->NZ, h->My, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   h->vel_fresh = false;
+  return DNS_OK;
+}
+
+int dns_set_forcing(dns_handle* h, int member0, int count, const double* f_lapv, const double* f_eta,
+                    int on_device) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    dns_handle* sh;
+    int m0;
+    const int rc = route(h, member0, count, &sh, &m0);
+    return rc ? rc : forward(h, sh, dns_set_forcing(sh, m0, count, f_lapv, f_eta, on_device));
+  }
+  if (!f_lapv && !f_eta) {
+    if (h->forcing_on) {
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      h->forcing_on = false;
+      invalidate_graph(h);
+    }
+    return DNS_OK;
+  }
+  if (member0 < 0 || count < 1 || member0 + count > h->E)
+    return fail(h, DNS_E_INVALID, "member range out of bounds");
+  const size_t full = size_t(h->E) * h->K * h->N * 2 * sizeof(double);
+  // the stream may still run a step that reads the forcing or the staging buffer
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (!h->fv) {
+    HIP_OR_FAIL(h, hipMalloc(reinterpret_cast<void**>(&h->fv), full));
+    HIP_OR_FAIL(h, hipMalloc(reinterpret_cast<void**>(&h->feta), full));
+    HIP_OR_FAIL(h, hipMemsetAsync(h->fv, 0, full, h->stream));
+    HIP_OR_FAIL(h, hipMemsetAsync(h->feta, 0, full, h->stream));
+  }
+  const size_t nspec = size_t(count) * h->K * h->N * 2;
+  const int rc = ensure_staging(h, 2 * nspec * sizeof(double));
+  if (rc) return rc;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  double* st = h->staging;
+  if (f_lapv) HIP_OR_FAIL(h, hipMemcpyAsync(st, f_lapv, nspec * sizeof(double), kind, h->stream));
+  else HIP_OR_FAIL(h, hipMemsetAsync(st, 0, nspec * sizeof(double), h->stream));
+  if (f_eta) HIP_OR_FAIL(h, hipMemcpyAsync(st + nspec, f_eta, nspec * sizeof(double), kind, h->stream));
+  else HIP_OR_FAIL(h, hipMemsetAsync(st + nspec, 0, nspec * sizeof(double), h->stream));
+  HIP_OR_FAIL(h, launch_state_to_device(st, h->fv, member0, count, h->E, h->K, h->N, h->stream));
+  HIP_OR_FAIL(h, launch_state_to_device(st + nspec, h->feta, member0, count, h->E, h->K, h->N, h->stream));
+  if (h->shared_mean)
+    HIP_OR_FAIL(h, launch_share_columns(h->fv, h->feta, nullptr, nullptr, h->E, h->N, h->NZ, h->My, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (!h->forcing_on) {
+    h->forcing_on = true;
+    invalidate_graph(h);
+  }
   return DNS_OK;
 }
 
@@ -1176,7 +1273,7 @@ bool cache_lookup(const dns_handle* h, const char* path, dns_tuning* t) {
     const int got = std::sscanf(line, "%d %d %d %d %d %d %d %lf %lf %d", &p, &nx, &ny, &nz, &e, &rows, &mem,
                                 &pm, &mm, &form);
     if (got != 9 && got != 10) continue;
-    if (p == h->precision && nx == h->Nx && ny == h->Ny && nz == h->Nz && e == h->E && form == h->advection) {
+    if (p == h->precision && nx == h->Nx && ny == h->Ny && nz == h->Nz && e == h->E && form == plane_form(h)) {
       t->plane_rows = rows;
       t->mode_members = mem;
       t->plane_ms = pm;
@@ -1203,19 +1300,18 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
     const int rc = refresh_velocities(h);
     if (rc) return rc;
   }
-  const int pi = h->precision == DNS_PREC_FP64 ? 0 : 1;
   int rows[3];
-  const int nv = plane_variants(h->precision, h->Nx, rows);
+  const int nv = plane_variants(h->precision, plane_form(h), h->Nx, rows);
   int best_v = 0;
   double best_p = 1e30;
   for (int v = 0; v < nv; ++v) {
-    h->plane_var[pi] = v;
+    plane_var(h) = v;
     double ms;
     const int rc = time_launches(h, kReps, [&] { return plane_launch(h, false); }, &ms);
     if (rc) return rc;
     if (ms < best_p) best_p = ms, best_v = v;
   }
-  h->plane_var[pi] = best_v;
+  plane_var(h) = best_v;
   // the mode kernel's second sub-step on the current stage buffers (the next
   // step rewrites its history first)
   int best_et = h->ET;
@@ -1240,7 +1336,7 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
     std::FILE* f = std::fopen(cache, "a");
     if (!f) return fail(h, DNS_E_INVALID, std::string("cannot append to tune cache ") + cache);
     std::fprintf(f, "%s %d %d %.6f %.6f %d\n", tune_key(h).c_str(), t.plane_rows, t.mode_members, t.plane_ms,
-                 t.mode_ms, h->advection);
+                 t.mode_ms, plane_form(h));
     std::fclose(f);
   }
   if (out) *out = t;
@@ -1342,6 +1438,8 @@ int dns_set_channels(dns_handle* h, int member0, int count, const float* in) {
                                       h->E, h->L, h->NZ, Mx, Mz, member0, count, h->kxs, h->kzs, h->Ubot, h->Utop,
                                       h->stream));
   HIP_OR_FAIL(h, hipMemsetAsync(h->failed + member0, 0, sizeof(int) * count, h->stream));
+  if (h->shared_mean)
+    HIP_OR_FAIL(h, launch_share_columns(h->v, h->eta, h->U, h->W, h->E, h->N, h->NZ, h->My, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   h->vel_fresh = false;
   return DNS_OK;

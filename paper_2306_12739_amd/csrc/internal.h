@@ -73,6 +73,9 @@ struct ModeArgs {
   const double* green_h;   // [N]: halves of the pressure-gradient response
   const double* ccw_h;     // [Fe]: Clenshaw-Curtis weights summed over node pairs
   // per-member outputs
+  // external forcing of Lap v and eta, state layout (nullptr: none)
+  const double* fv;
+  const double* feta;
   double* gamma;        // [E]
   int* failed;          // [E]
   unsigned long long* divmax;  // [E] (bit pattern of a non-negative double)
@@ -86,12 +89,14 @@ struct ModeArgs {
 };
 
 // Kernel launchers (kernels_*.hip).  Return hipSuccess or the launch error.
-// form 0: advective u . grad u; 1: rotational omega x u
+// form 0: advective u . grad u; 1: rotational omega x u; 2: quasi-linear
+// advective (n_x >= 1 output linearised about the streamwise mean)
+constexpr int kPlaneForms = 3;
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s);
-// Chunk-row counts of the plane-kernel variants built for (precision, Nx);
-// returns how many (<= 3), index 0 being the default.
-int plane_variants(int precision, int Nx, int* rows);
+// Chunk-row counts of the plane-kernel variants built for (precision, form,
+// Nx); returns how many (<= 3), index 0 being the default.
+int plane_variants(int precision, int form, int Nx, int* rows);
 bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
 // Resolve kernels on the current device before any graph capture uses them.
@@ -118,6 +123,15 @@ std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm);
 // M[i][k] +/- M[i][Cn-1-k] (the centre column alone for even, odd Cn), rows
 // i < rows_out are the first-half rows of M.
 std::vector<double> half_block(const double* M, int rows_out, int Cn, int ldm, bool even_in);
+
+// Shared-mean ensembles: member averages of the n_x = 0 column (modes k < NZ)
+// of the advection terms and plane means (in place, every member), and of the
+// n_x = 0 column of two state-shaped buffers plus, if U is non-null, the mean
+// profiles U, W.
+hipError_t launch_member_mean(int precision, void* nl, double* means, int My, int E, int K, int NZ,
+                              hipStream_t s);
+hipError_t launch_share_columns(double* v, double* eta, double* U, double* W, int E, int N, int NZ,
+                                int My, hipStream_t s);
 
 // layout transposes between the host state layout and the device layout
 hipError_t launch_state_to_device(const double* host_layout_dev, double* dev, int E0, int count,

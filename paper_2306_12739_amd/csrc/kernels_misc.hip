@@ -118,7 +118,92 @@ __global__ void stats_kernel(StatsArgs a, int accumulate) {
   }
 }
 
+// Shared-mean ensembles (Sec. 4, statistical-state-dynamics paragraph): every
+// member's streamwise mean is the member average.  member_mean replaces the
+// n_x = 0 column (modes k < NZ) of each plane's advection terms and the plane
+// means by their member averages, summed in member order; share_columns does the
+// same for the n_x = 0 column of state-shaped buffers [K][N][E] (complex) and,
+// when U is given, for the mean profiles [My][E].
+template <typename VT>
+__global__ void member_mean(VT* __restrict__ nl, double* __restrict__ means, int My, int E, int K,
+                            int NZ) {
+  const size_t ncol = size_t(3) * My * NZ, total = ncol + size_t(2) * My;
+  const double inv = 1.0 / E;
+  for (size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x; idx < total;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    if (idx < ncol) {
+      const int k = int(idx % NZ);
+      const size_t fj = idx / NZ;  // f * My + j
+      VT* base = nl + 2 * (fj * E * K + k);
+      double re = 0.0, im = 0.0;
+      for (int e = 0; e < E; ++e) {
+        re += double(base[2 * size_t(e) * K]);
+        im += double(base[2 * size_t(e) * K + 1]);
+      }
+      const VT r = VT(re * inv), i = VT(im * inv);
+      for (int e = 0; e < E; ++e) {
+        base[2 * size_t(e) * K] = r;
+        base[2 * size_t(e) * K + 1] = i;
+      }
+    } else {
+      double* row = means + (idx - ncol) * E;  // [2][My] rows of E members
+      double sum = 0.0;
+      for (int e = 0; e < E; ++e) sum += row[e];
+      for (int e = 0; e < E; ++e) row[e] = sum * inv;
+    }
+  }
+}
+
+__global__ void share_columns(double* __restrict__ v, double* __restrict__ eta, double* __restrict__ U,
+                              double* __restrict__ W, int E, int N, int NZ, int My) {
+  const size_t ncol = size_t(NZ) * N;  // complex elements of the n_x = 0 column
+  const size_t total = 2 * ncol + (U ? size_t(2) * My : 0);
+  const double inv = 1.0 / E;
+  for (size_t idx = blockIdx.x * size_t(blockDim.x) + threadIdx.x; idx < total;
+       idx += size_t(gridDim.x) * blockDim.x) {
+    if (idx < 2 * ncol) {
+      double* base = (idx < ncol ? v : eta) + 2 * (idx % ncol) * E;  // [k][j] row of E members
+      double re = 0.0, im = 0.0;
+      for (int e = 0; e < E; ++e) {
+        re += base[2 * e];
+        im += base[2 * e + 1];
+      }
+      re *= inv;
+      im *= inv;
+      for (int e = 0; e < E; ++e) {
+        base[2 * e] = re;
+        base[2 * e + 1] = im;
+      }
+    } else {
+      const size_t r = idx - 2 * ncol;
+      double* row = (r < size_t(My) ? U : W) + (r % My) * E;
+      double sum = 0.0;
+      for (int e = 0; e < E; ++e) sum += row[e];
+      for (int e = 0; e < E; ++e) row[e] = sum * inv;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_member_mean(int precision, void* nl, double* means, int My, int E, int K, int NZ,
+                              hipStream_t s) {
+  const size_t total = size_t(3) * My * NZ + size_t(2) * My;
+  if (precision == 0)
+    hipLaunchKernelGGL(member_mean<double>, dim3(grid_for(total)), dim3(256), 0, s,
+                       static_cast<double*>(nl), means, My, E, K, NZ);
+  else
+    hipLaunchKernelGGL(member_mean<float>, dim3(grid_for(total)), dim3(256), 0, s,
+                       static_cast<float*>(nl), means, My, E, K, NZ);
+  return hipGetLastError();
+}
+
+hipError_t launch_share_columns(double* v, double* eta, double* U, double* W, int E, int N, int NZ,
+                                int My, hipStream_t s) {
+  const size_t total = 2 * size_t(NZ) * N + (U ? size_t(2) * My : 0);
+  hipLaunchKernelGGL(share_columns, dim3(grid_for(total)), dim3(256), 0, s, v, eta, U, W, E, N, NZ, My);
+  return hipGetLastError();
+}
 
 hipError_t launch_state_to_device(const double* src, double* dst, int E0, int count, int E, int K,
                                   int N, hipStream_t s) {
@@ -150,11 +235,14 @@ hipError_t launch_profile_from_device(const double* src, double* dst, int E0, in
 
 // Resolve the statistics and layout kernels on the current device.
 hipError_t misc_preload() {
-  const void* fns[5] = {reinterpret_cast<const void*>(&stats_kernel),
+  const void* fns[8] = {reinterpret_cast<const void*>(&stats_kernel),
                         reinterpret_cast<const void*>(&state_to_device),
                         reinterpret_cast<const void*>(&state_from_device),
                         reinterpret_cast<const void*>(&profile_to_device),
-                        reinterpret_cast<const void*>(&profile_from_device)};
+                        reinterpret_cast<const void*>(&profile_from_device),
+                        reinterpret_cast<const void*>(&member_mean<double>),
+                        reinterpret_cast<const void*>(&member_mean<float>),
+                        reinterpret_cast<const void*>(&share_columns)};
   for (const void* fn : fns) {
     hipFuncAttributes attr;
     const hipError_t err = hipFuncGetAttributes(&attr, fn);

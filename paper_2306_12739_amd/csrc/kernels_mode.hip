@@ -287,6 +287,23 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
         const int rowX = even ? kk : 2 * He + kk;
         double Fr = S[rowF * CRP + 2 * c], Fi = S[rowF * CRP + 2 * c + 1];
         double Gr = S2[rowF * CRP + 2 * c], Gi = S2[rowF * CRP + 2 * c + 1];
+        if (a.fv) {
+          // external forcing held over the step enters every sub-step's terms
+          // as F - f_lapv, G - f_eta (y-parity halves of the interior values)
+          const size_t f1 = st(kk, c), f2 = st(N - 1 - kk, c);
+          const double sgn = even ? 1.0 : -1.0;
+          if (even && kk == Ho) {
+            Fr -= a.fv[f1];
+            Fi -= a.fv[f1 + 1];
+            Gr -= a.feta[f1];
+            Gi -= a.feta[f1 + 1];
+          } else {
+            Fr -= 0.5 * (a.fv[f1] + sgn * a.fv[f2]);
+            Fi -= 0.5 * (a.fv[f1 + 1] + sgn * a.fv[f2 + 1]);
+            Gr -= 0.5 * (a.feta[f1] + sgn * a.feta[f2]);
+            Gi -= 0.5 * (a.feta[f1 + 1] + sgn * a.feta[f2 + 1]);
+          }
+        }
         const size_t so = st(hr, c);
         double* hf = a.hF + so;
         double* hg = a.hG + so;

@@ -27,6 +27,19 @@
 // is formed in the z fold, so a chunk needs 6 z- and 6 x-transforms:
 //   Z1 -> X1 phys u, v, w;  ZW z-iFFT(omega) -> XW phys omega;
 //   P  N = (oy w - oz v, oz u - ox w, ox v - oy u), plane sums.
+//
+// Quasi-linear form (kForm 2, the perturbation dynamics of a shared-mean
+// ensemble): with U_m the streamwise mean (n_x = 0 part) of each field and
+// u' = u - U_m, the n_x >= 1 output is U_m . grad u' + u' . grad U_m and the
+// n_x = 0 output is the full advection's.  On a physical row (fixed y, z) the
+// streamwise mean of a field is the real part of its n_x = 0 z-transformed
+// value, so the chunk keeps those row means of u, v, w and of the z- and
+// y-derivatives, accumulates the linear terms
+//   Lin_i = U_m du_i/dx + W_m (du_i/dz - <du_i/dz>) + (w - W_m) <du_i/dz>
+//         + V_m (du_i/dy - <du_i/dy>) + (v - V_m) <du_i/dy>
+// (their row means vanish) beside the full products, and hands the forward
+// transform Lin_i + (row mean of the full product): its n_x = 0 mode is the
+// full advection's and every other mode is the linear term's.
 #include <type_traits>
 
 #include "fft.h"
@@ -66,7 +79,8 @@ __device__ __forceinline__ void stc(VT* p, cx<T> c) {
   *reinterpret_cast<V*>(p) = v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -101,8 +115,9 @@ struct PlaneCfg {
 
 }  // namespace
 
-template <typename T, typename VT, int L, int P, int PP, bool kRot>
+template <typename T, typename VT, int L, int P, int PP, int kForm>
 __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
+  constexpr bool kRot = kForm == 1, kQL = kForm == 2;
   using C = cx<T>;
   using Cfg = PlaneCfg<T, L, P, PP>;
   constexpr int MX = Cfg::MX, MZ = Cfg::MZ, NZ = Cfg::NZ, R = Cfg::R, PH = Cfg::PH;
@@ -113,6 +128,10 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   __shared__ C mid[Cfg::MID];
   __shared__ T phys[NPHYS][Cfg::NPTS];
   __shared__ double red[8][kNT / 64];
+  // quasi-linear form: linear terms and row means (1-element stand-ins otherwise)
+  __shared__ T lin[kQL ? 3 : 1][kQL ? Cfg::NPTS : 1];
+  __shared__ T rmean[kQL ? 8 : 1][kQL ? PP : 1];   // U_m V_m W_m, <d/dz> x3, <du/dy> <dw/dy>
+  __shared__ T rsum[kQL ? 3 : 1][kQL ? PP : 1];
 
   const int tid = threadIdx.x;
   const int flat = xcd_logical(blockIdx.x, gridDim.x);
@@ -243,8 +262,20 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     std::integral_constant<int, 1> dz;
     std::integral_constant<int, 2> vort;
 
+    // quasi-linear form: row means of NF fields from the n_x = 0 entries of zb
+    auto keep_row_means = [&](int nf, int slot) {
+      if constexpr (kQL) {
+        for (int t = tid; t < nf * PP; t += kNT) {
+          const int fi = t / PP, q = t - fi * PP;
+          rmean[slot + fi][q] = zb[(fi * PP + q) * Cfg::ZP].x;
+        }
+        __syncthreads();
+      }
+    };
+
     zinv(three, 0, plain);
     __syncthreads();
+    keep_row_means(3, 0);
     xinv(three, false, [&](int fi, int p, T val) { phys[PU + fi][p] = val; });
     __syncthreads();
     if constexpr (kRot) {
@@ -274,6 +305,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     } else {
     xinv(three, true, [&](int fi, int p, T val) {
       const T u = phys[PU][p];
+      if constexpr (kQL) lin[fi][p] = rmean[0][p / Cfg::MXP] * val;
       if (fi == 0) {
         phys[PNU][p] = u * val;
         phys[PVY][p] = -val;
@@ -287,8 +319,14 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     __syncthreads();
     zinv(three, 0, dz);
     __syncthreads();
+    keep_row_means(3, 3);
     xinv(three, false, [&](int fi, int p, T val) {
       const T w = phys[PW][p];
+      if constexpr (kQL) {
+        const int q = p / Cfg::MXP;
+        const T Wm = rmean[2][q], Zm = rmean[3 + fi][q];
+        lin[fi][p] += Wm * (val - Zm) + (w - Wm) * Zm;
+      }
       if (fi == 0) {
         phys[PNU][p] += w * val;
       } else if (fi == 1) {
@@ -302,8 +340,14 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     __syncthreads();
     zinv(two, 3, plain);
     __syncthreads();
+    keep_row_means(2, 6);
     xinv(two, false, [&](int fi, int p, T val) {
       const T v = phys[PV][p];
+      if constexpr (kQL) {
+        const int q = p / Cfg::MXP;
+        const T Vm = rmean[1][q], Ym = rmean[6 + fi][q];
+        lin[fi == 0 ? 0 : 2][p] += Vm * (val - Ym) + (v - Vm) * Ym;
+      }
       if (fi == 0) phys[PNU][p] += v * val; else phys[PNW][p] += v * val;
       if (want_stats) s_grad += double(val) * double(val);
     });
@@ -313,6 +357,10 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       const int p = q * Cfg::MXP + (pl - q * MX);
       const T u = phys[PU][p], v = phys[PV][p], w = phys[PW][p], vy = phys[PVY][p];
       phys[PNV][p] += v * vy;
+      if constexpr (kQL) {  // <dv/dy> = -<dw/dz> by continuity (<du/dx> = 0)
+        const T Vm = rmean[1][q], Ym = -rmean[5][q];
+        lin[1][p] += Vm * (vy - Ym) + (v - Vm) * Ym;
+      }
       s_uv += double(u) * double(v);
       s_wv += double(w) * double(v);
       if (want_stats) {
@@ -324,6 +372,27 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     }
     }  // advective form
     __syncthreads();
+    if constexpr (kQL) {
+      static_assert(MX <= 128, "row sums take at most two values per lane");
+      // row sums of the full products, one wavefront per row, fixed order
+      const int lane = tid & 63, wvi = tid >> 6;
+      for (int rr = wvi; rr < 3 * PP; rr += kNT / 64) {
+        const int i = rr / PP, q = rr - i * PP;
+        const T* row = &phys[PNU + i][q * Cfg::MXP];
+        T x = lane < MX ? row[lane] : T(0);
+        if (lane + 64 < MX) x += row[lane + 64];
+        x = wave_sum(x);
+        if (lane == 0) rsum[i][q] = x;
+      }
+      __syncthreads();
+      for (int pl = tid; pl < Cfg::NPT; pl += kNT) {
+        const int q = pl / MX;
+        const int p = q * Cfg::MXP + (pl - q * MX);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) phys[PNU + i][p] = lin[i][p] + rsum[i][q] * (T(1) / T(MX));
+      }
+      __syncthreads();
+    }
     // ---- forward x transform of (Nu, Nv, Nw); keep |kx| < L ----------------
     {
       auto load = [&](int b, int n) -> C {
@@ -423,55 +492,77 @@ constexpr int kVar64[4][3] = {{24, 12, 8}, {16, 24, 8}, {12, 8, 0}, {16, 12, 8}}
 constexpr int kVar32[4][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 16}};
 int grid_index(int Nx) { return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : -1; }
 
-template <typename T, int L, int PP>
+template <typename T, int L, int PP, int Form>
 constexpr bool variant_built() {
   constexpr int gi = L == 8 ? 0 : L == 16 ? 1 : L == 24 ? 2 : L == 32 ? 3 : -1;
   if constexpr (gi < 0 || (3 * L) % PP != 0) {
     return false;
   } else {
-    if (PlaneCfg<T, L, L, PP>::kLdsBytes > 160 * 1024) return false;
+    using Cfg = PlaneCfg<T, L, L, PP>;
+    const size_t extra = Form == 2 ? (3 * Cfg::NPTS + 11 * PP) * sizeof(T) : 0;
+    if (Cfg::kLdsBytes + extra > 160 * 1024) return false;
     for (int v = 0; v < 3; ++v)
       if ((sizeof(T) == 8 ? kVar64 : kVar32)[gi][v] == PP) return true;
     return false;
   }
 }
 
-template <typename T, int L, int PP, bool Rot>
+template <typename T, int L, int PP, int Form>
 const void* plane_fn_if_built() {
-  if constexpr (variant_built<T, L, PP>())
-    return reinterpret_cast<const void*>(&plane_kernel<T, T, L, L, PP, Rot>);
+  if constexpr (variant_built<T, L, PP, Form>())
+    return reinterpret_cast<const void*>(&plane_kernel<T, T, L, L, PP, Form>);
   return nullptr;
 }
 
-template <typename T, int L, bool Rot>
+template <typename T, int L, int Form>
 const void* plane_fn_rows(int pp) {
   switch (pp) {
-    case 8: return plane_fn_if_built<T, L, 8, Rot>();
-    case 12: return plane_fn_if_built<T, L, 12, Rot>();
-    case 16: return plane_fn_if_built<T, L, 16, Rot>();
-    case 24: return plane_fn_if_built<T, L, 24, Rot>();
-    case 32: return plane_fn_if_built<T, L, 32, Rot>();
-    case 36: return plane_fn_if_built<T, L, 36, Rot>();
-    case 48: return plane_fn_if_built<T, L, 48, Rot>();
+    case 8: return plane_fn_if_built<T, L, 8, Form>();
+    case 12: return plane_fn_if_built<T, L, 12, Form>();
+    case 16: return plane_fn_if_built<T, L, 16, Form>();
+    case 24: return plane_fn_if_built<T, L, 24, Form>();
+    case 32: return plane_fn_if_built<T, L, 32, Form>();
+    case 36: return plane_fn_if_built<T, L, 36, Form>();
+    case 48: return plane_fn_if_built<T, L, 48, Form>();
   }
   return nullptr;
 }
 
-template <typename T, bool Rot>
+template <typename T, int Form>
 const void* plane_fn_grid(int Nx, int pp) {
   switch (Nx) {
-    case 16: return plane_fn_rows<T, 8, Rot>(pp);
-    case 32: return plane_fn_rows<T, 16, Rot>(pp);
-    case 48: return plane_fn_rows<T, 24, Rot>(pp);
-    case 64: return plane_fn_rows<T, 32, Rot>(pp);
+    case 16: return plane_fn_rows<T, 8, Form>(pp);
+    case 32: return plane_fn_rows<T, 16, Form>(pp);
+    case 48: return plane_fn_rows<T, 24, Form>(pp);
+    case 64: return plane_fn_rows<T, 32, Form>(pp);
   }
   return nullptr;
 }
 
-// The kernel of (precision, advection form, grid, chunk rows); nullptr if not built.
+template <typename T>
+const void* plane_fn_t(int form, int Nx, int pp) {
+  switch (form) {
+    case 0: return plane_fn_grid<T, 0>(Nx, pp);
+    case 1: return plane_fn_grid<T, 1>(Nx, pp);
+    case 2: return plane_fn_grid<T, 2>(Nx, pp);
+  }
+  return nullptr;
+}
+
+// The kernel of (precision, form, grid, chunk rows); nullptr if not built.
 const void* plane_fn(int precision, int form, int Nx, int pp) {
-  if (precision == 0) return form ? plane_fn_grid<double, true>(Nx, pp) : plane_fn_grid<double, false>(Nx, pp);
-  return form ? plane_fn_grid<float, true>(Nx, pp) : plane_fn_grid<float, false>(Nx, pp);
+  return precision == 0 ? plane_fn_t<double>(form, Nx, pp) : plane_fn_t<float>(form, Nx, pp);
+}
+
+// chunk-row counts of the table row for (precision, Nx), built or not
+int table_rows(int precision, int Nx, int* rows) {
+  const int gi = grid_index(Nx);
+  if (gi < 0) return 0;
+  const int(*tab)[3] = precision == 0 ? kVar64 : kVar32;
+  int n = 0;
+  for (int v = 0; v < 3; ++v)
+    if (tab[gi][v]) rows[n++] = tab[gi][v];
+  return n;
 }
 }  // namespace
 
@@ -479,14 +570,15 @@ bool plane_supported(int Nx, int Nz) {
   return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64);
 }
 
-// Resolve every built plane-kernel variant of grid Nx (both precisions, both
-// advection forms) on the current device, so that a later graph capture never
-// holds a kernel's first launch.
+// Resolve every built plane-kernel variant of grid Nx (both precisions, every
+// form) on the current device, so that a later graph capture never holds a
+// kernel's first launch.
 hipError_t plane_preload(int Nx) {
   for (int prec = 0; prec < 2; ++prec) {
-    int rows[3];
-    const int n = plane_variants(prec, Nx, rows);
-    for (int form = 0; form < 2; ++form) {
+    for (int form = 0; form < kPlaneForms; ++form) {
+      int rows[3];
+      const int n = plane_variants(prec, form, Nx, rows);
+      if (n == 0) return hipErrorInvalidValue;
       for (int v = 0; v < n; ++v) {
         const void* fn = plane_fn(prec, form, Nx, rows[v]);
         if (!fn) return hipErrorInvalidValue;
@@ -499,23 +591,24 @@ hipError_t plane_preload(int Nx) {
   return hipSuccess;
 }
 
-int plane_variants(int precision, int Nx, int* rows) {
-  const int gi = grid_index(Nx);
-  if (gi < 0) return 0;
-  const int(*tab)[3] = precision == 0 ? kVar64 : kVar32;
+// The table's variants that are built for this form (the quasi-linear form
+// needs more LDS and drops the largest chunks).
+int plane_variants(int precision, int form, int Nx, int* rows) {
+  int all[3];
+  const int n_all = table_rows(precision, Nx, all);
   int n = 0;
-  for (int v = 0; v < 3; ++v)
-    if (tab[gi][v]) rows[n++] = tab[gi][v];
+  for (int v = 0; v < n_all; ++v)
+    if (plane_fn(precision, form, Nx, all[v])) rows[n++] = all[v];
   return n;
 }
 
 // precision 0: FP64 storage and arithmetic; 1: FP32 storage and FFT arithmetic.
-// form 0: advective u . grad u; 1: rotational omega x u.
+// form 0: advective u . grad u; 1: rotational omega x u; 2: quasi-linear advective.
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s) {
-  if (!plane_supported(Nx, Nz) || (form != 0 && form != 1)) return hipErrorInvalidValue;
+  if (!plane_supported(Nx, Nz) || form < 0 || form >= kPlaneForms) return hipErrorInvalidValue;
   int rows[3];
-  const int n = plane_variants(precision, Nx, rows);
+  const int n = plane_variants(precision, form, Nx, rows);
   if (variant < 0 || variant >= n) return hipErrorInvalidValue;
   const void* fn = plane_fn(precision, form, Nx, rows[variant]);
   if (!fn) return hipErrorInvalidValue;

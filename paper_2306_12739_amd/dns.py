@@ -34,6 +34,8 @@ OPT_PLANE_ROWS = 5
 OPT_MODE_TILE = 6
 OPT_CHAINS = 7
 OPT_ADVECTION = 8
+OPT_SHARED_MEAN = 9
+OPT_QUASILINEAR = 10
 
 ADV_ADVECTIVE = 0
 ADV_ROTATIONAL = 1
@@ -46,7 +48,7 @@ EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "d
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",
             "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
             "dns_create_grouped", "dns_group_handle", "dns_tune",
-            "dns_get_channels", "dns_set_channels",
+            "dns_get_channels", "dns_set_channels", "dns_set_forcing",
             "sno_create", "sno_set_option", "sno_num_params", "sno_set_params", "sno_get_params",
             "sno_forward", "sno_loss_grad", "sno_train_step", "sno_sync", "sno_last_error",
             "sno_destroy"]
@@ -142,6 +144,7 @@ def library(path=LIB_PATH):
     lib.dns_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     lib.dns_get_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     lib.dns_set_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.dns_set_forcing.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int]
     lib.sno_create.argtypes = [ctypes.POINTER(SnoConfig), ctypes.c_ulonglong, ctypes.POINTER(vp)]
     lib.sno_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
     lib.sno_num_params.argtypes = [vp]
@@ -267,6 +270,19 @@ class Ensemble:
             raise ValueError("state arrays do not match the grid")
         sv = StateView(v.ctypes.data, eta.ctypes.data, U.ctypes.data, W.ctypes.data, 0)
         return self._check(self.lib.dns_set_state(self.h, member0, count, ctypes.byref(sv)))
+
+    def set_forcing(self, f_lapv=None, f_eta=None, member0=0):
+        """Additive (Lap v, eta) forcing, host arrays in the state layout of
+        v/eta (None: zero); both None turns the forcing off."""
+        if f_lapv is None and f_eta is None:
+            return self._check(self.lib.dns_set_forcing(self.h, member0, 0, None, None, 0))
+        arrs = [None if f is None else np.ascontiguousarray(f, dtype=np.complex128) for f in (f_lapv, f_eta)]
+        count = next(a.shape[0] for a in arrs if a is not None)
+        for a in arrs:
+            if a is not None and a.shape != (count,) + self.shape_spec:
+                raise ValueError("forcing arrays do not match the grid")
+        ptrs = [None if a is None else a.ctypes.data for a in arrs]
+        return self._check(self.lib.dns_set_forcing(self.h, member0, count, ptrs[0], ptrs[1], 0))
 
     def set_state_device(self, v, eta, U, W, member0=0):
         """torch device tensors (complex128 / float64, contiguous)."""
