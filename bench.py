@@ -147,9 +147,22 @@ def cpu_baseline(w, name):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
     except OSError:
         pass
+    # the smaller workloads: the 2-member Couette case run fully, one step of all
+    # 64 members of the 32x49x32 case (same threads)
+    others = {}
+    for oname, E, nsteps in (("couette-re400-16x33x16-e2", 2, 100), ("couette-re600-32x49x32-e64", 64, 1)):
+        ow = inputs.WORKLOADS[oname]
+        osim = oracle.OracleDNS(ow["flow"], ow["Re"], ow["Lx"], ow["Lz"], ow["Nx"], ow["Ny"], ow["Nz"], E,
+                                ow["dt"])
+        osim.set_state(*inputs.workload_state(oname, ensemble=E))
+        t1 = time.perf_counter()
+        osim.step(nsteps)
+        others[oname] = {"member_steps_per_s": E * nsteps / (time.perf_counter() - t1),
+                         "sample": f"{E} members x {nsteps} steps"}
     return {"value": members * steps / dt, "unit": "member-steps/s", "cores": int(cores),
             "kind": "oracle", "cpu_model": model, "value_1_thread": one,
-            "sample": f"{members} members x {steps} steps of {name} (numpy FP64, operators prebuilt)"}
+            "sample": f"{members} members x {steps} steps of {name} (numpy FP64, operators prebuilt)",
+            "other_workloads": others}
 
 
 def serial_gpu(w, precision, stream, steps=50):

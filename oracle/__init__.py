@@ -23,6 +23,8 @@ ensemble DNS") step by step, in the paper's order and notation:
 * ``s3t``         -- approximate S3T ensemble (Sec. 4): members sharing one
                      streamwise-mean flow, quasi-linear perturbations,
                      additive (Lap v, eta) forcing.
+* ``optimal``     -- optimal disturbances of a frozen streamwise-mean flow by
+                     forward-adjoint iteration with Gram-Schmidt (App. B).
 * ``sno``         -- learned spin-up (not in the paper): channel form of a
                      state and back to an admissible state, a spectral neural
                      operator with its gradient, AdamW.
@@ -40,9 +42,10 @@ from .step import OracleDNS
 from .s3t import OracleS3T
 from . import diagnostics
 from . import sno
+from . import optimal
 
 __all__ = [
     "nodes", "diff_matrix", "dirichlet_d2", "clamped_matrices",
     "clenshaw_curtis_weights", "SpectralGrid", "ModeOperators",
-    "MeanOperators", "OracleDNS", "OracleS3T", "diagnostics", "sno",
+    "MeanOperators", "OracleDNS", "OracleS3T", "diagnostics", "sno", "optimal",
 ]

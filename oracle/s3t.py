@@ -22,6 +22,14 @@ operator acting on a (Lap v, eta) state.  In this module:
   enters each step exactly once).  With the sign conventions of OracleDNS.rhs
   (d Lap v/dt = -F + ..., d eta/dt = -G + ...) this is F -> F - f_lapv,
   G -> G - f_eta.
+* frozen_mean=True keeps the streamwise mean fixed (a base flow), so that the
+  linear perturbation dynamics are those of the Navier-Stokes equations
+  linearised about it (App. B); perturbation="adjoint" advances the adjoint of
+  that linearised advection backwards in time: for a velocity lambda' of the
+  n_x >= 1 modes the advection term is -(U_m . grad) lambda' + (grad U_m)^T lambda',
+  i.e. component j is -U_m . grad lambda'_j + sum_i lambda'_i d_j U_m,i (with the
+  mean divergence-free and V_m = 0 at the walls; the viscous and pressure parts
+  are self-adjoint, so the same CN operators serve both directions).
 """
 
 import numpy as np
@@ -32,10 +40,11 @@ from .step import OracleDNS
 class OracleS3T(OracleDNS):
     """Shared-mean ensemble with optional quasi-linear perturbations and forcing."""
 
-    def __init__(self, *args, perturbation="linear", **kw):
-        if perturbation not in ("linear", "nonlinear"):
-            raise ValueError("perturbation must be 'linear' or 'nonlinear'")
+    def __init__(self, *args, perturbation="linear", frozen_mean=False, **kw):
+        if perturbation not in ("linear", "nonlinear", "adjoint"):
+            raise ValueError("perturbation must be 'linear', 'nonlinear' or 'adjoint'")
         self.perturbation = perturbation
+        self.frozen_mean = frozen_mean
         super().__init__(*args, **kw)
         if self.advection != "convective":
             raise ValueError("the shared-mean ensemble uses the advective form")
@@ -85,6 +94,40 @@ class OracleS3T(OracleDNS):
                 out[i][e] = g.to_spectral(n)
         return out
 
+    def transpose_advect(self, a, b):
+        """Dealiased component j = sum_i a_i d_j b_i, truncated."""
+        g = self.grid
+        P = g.to_physical
+        out = [np.zeros_like(b["u"]) for _ in range(3)]
+        for e in range(b["u"].shape[0]):
+            aa = [P(a[f][e]) for f in ("u", "v", "w")]
+            for j, d in enumerate(("x", "y", "z")):
+                n = 0.0
+                for i, f in enumerate(("u", "v", "w")):
+                    if d == "x":
+                        db = P(1j * g.KX * b[f][e])
+                    elif d == "z":
+                        db = P(1j * g.KZ * b[f][e])
+                    else:
+                        db = P(b[f + "y"][e])
+                    n = n + aa[i] * db
+                out[j][e] = g.to_spectral(n)
+        return out
+
+    def nonlinear_adjoint(self, vel):
+        """Adjoint of the linearised advection for the n_x >= 1 modes; the
+        n_x = 0 column (the frozen base flow's) is zero."""
+        m, p = self.split(vel)
+        mp = self.advect(m, p)
+        tr = self.transpose_advect(p, m)
+        out = []
+        for i in range(3):
+            x = -mp[i] + tr[i]
+            x[..., 0, :] = 0.0
+            out.append(x)
+        uv, wv = self.plane_means(vel)
+        return out[0], out[1], out[2], uv, wv
+
     def plane_means(self, vel):
         P = self.grid.to_physical
         E = vel["u"].shape[0]
@@ -117,6 +160,8 @@ class OracleS3T(OracleDNS):
         vel = self.velocities(*x)
         if self.perturbation == "linear":
             N = self.nonlinear_quasilinear(vel)
+        elif self.perturbation == "adjoint":
+            N = self.nonlinear_adjoint(vel)
         else:
             N = self.nonlinear(vel)
         F, G, EU, EW = self.rhs(*N)
@@ -130,3 +175,10 @@ class OracleS3T(OracleDNS):
         EU = np.broadcast_to(EU.mean(axis=0), EU.shape).copy()
         EW = np.broadcast_to(EW.mean(axis=0), EW.shape).copy()
         return F, G, EU, EW
+
+    def solve(self, h, x0, Xc):
+        v, eta, U, W = super().solve(h, x0, Xc)
+        if self.frozen_mean:
+            v[:, 0], eta[:, 0] = x0[0][:, 0], x0[1][:, 0]
+            U, W = x0[2].copy(), x0[3].copy()
+        return v, eta, U, W
