@@ -137,9 +137,16 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  mean, U_m . grad u' + u' . grad U_m, while the
                                  mean keeps the full advection including the
                                  streamwise average of u' . grad u' (the second-
-                                 cumulant closure of S3T).  Advective form only
-                                 (DNS_E_INVALID with DNS_ADV_ROTATIONAL).  Fewer
-                                 plane-kernel chunk-row variants fit its LDS.
+                                 cumulant closure of S3T); 2 the adjoint of that
+                                 linearised advection, -(U_m . grad) l' +
+                                 (grad U_m)^T l' (App. B, integrated forward in
+                                 the reversed time; use with a frozen mean).
+                                 Advective form only (DNS_E_INVALID with
+                                 DNS_ADV_ROTATIONAL).  Fewer plane-kernel
+                                 chunk-row variants fit its LDS.  Default 0.    */
+#define DNS_OPT_FROZEN_MEAN 11 /* value: 1 steps leave the n_x = 0 modes and U00,
+                                 W00 as they are (a base flow for linearised or
+                                 adjoint perturbation dynamics, App. B).
                                  Default 0.                                     */
 #define DNS_MAX_CHAINS 4
 
@@ -207,6 +214,21 @@ int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s
  * Errors: DNS_E_INVALID (member range). */
 int dns_set_forcing(dns_handle* h, int member0, int count, const double* f_lapv, const double* f_eta,
                     int on_device);
+
+/* Kinetic energy density E = 1/(2V) int |u'|^2 of each member's perturbation
+ * (its n_x >= 1 modes), from the FP64 state; out has `ensemble` entries
+ * (App. B: the growth G(T) = E(T) / E(0)).  Synchronises the stream.
+ * Errors: DNS_E_INVALID (NULL output, grouped handle). */
+int dns_perturbation_energy(dns_handle* h, double* out);
+
+/* Modified Gram-Schmidt of the members, in member order, over their n_x >= 1
+ * modes in the kinetic-energy inner product, each normalised to energy density
+ * 1; the n_x = 0 modes and U00, W00 are left as they are (App. B: the
+ * orthonormalisation step of the forward-adjoint iteration that yields the
+ * leading optimal disturbances).  Runs on the host in FP64 over a copy of the
+ * state.  Errors: DNS_E_INVALID (a member without an independent
+ * perturbation, grouped handle). */
+int dns_orthonormalize(dns_handle* h);
 
 /* Copy members [member0, member0+count) into s (synchronises the stream). */
 int dns_get_state(dns_handle* h, int member0, int count, dns_state_view* s);

@@ -66,7 +66,9 @@ struct dns_handle {
   // shared-mean ensemble: one streamwise mean for all members, optionally
   // quasi-linear perturbations, and an additive (Lap v, eta) forcing
   bool shared_mean = false;
-  bool quasilinear = false;
+  int quasilinear = 0;        // 0 full advection, 1 linearised, 2 adjoint of the linearised
+  bool frozen_mean = false;   // sub-steps leave the n_x = 0 modes and U, W untouched
+  std::vector<double> host_D1c, host_ccw;  // for energy inner products on the host
   bool forcing_on = false;
   double *fv = nullptr, *feta = nullptr;
   // member chains advanced concurrently within a step
@@ -230,6 +232,7 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   a.Utop = h->Utop;
   a.Qtarget = h->flux;
   a.stage = stage;
+  a.freeze_mean = h->frozen_mean ? 1 : 0;
   a.poiseuille = h->flow == DNS_FLOW_POISEUILLE;
   return a;
 }
@@ -258,7 +261,7 @@ PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool wal
 }
 
 // plane-kernel form: 0 advective, 1 rotational, 2 quasi-linear advective
-int plane_form(const dns_handle* h) { return h->quasilinear ? 2 : h->advection; }
+int plane_form(const dns_handle* h) { return h->quasilinear ? 1 + h->quasilinear : h->advection; }
 int& plane_var(dns_handle* h) { return h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1][plane_form(h)]; }
 
 hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr,
@@ -534,6 +537,8 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     return fail(nullptr, DNS_E_INVALID, "a Crank-Nicolson operator is singular");
   }
   h->max_cond = ho.max_cond;
+  h->host_D1c = ho.D1c;
+  h->host_ccw = ho.ccw;
 
   auto fail_free = [&](int code, const std::string& msg) {
     free_all(h);
@@ -768,7 +773,7 @@ int dns_set_option(dns_handle* h, int key, long long value) {
   ORDER_AFTER_PARENT(h);
   if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS || key == DNS_OPT_CHAINS ||
                        key == DNS_OPT_ADVECTION || key == DNS_OPT_SHARED_MEAN ||
-                       key == DNS_OPT_QUASILINEAR)) {
+                       key == DNS_OPT_QUASILINEAR || key == DNS_OPT_FROZEN_MEAN)) {
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     for (dns_handle* sh : h->sub) {
       const int rc = dns_set_option(sh, key, value);
@@ -848,10 +853,15 @@ int dns_set_option(dns_handle* h, int key, long long value) {
       return DNS_OK;
     }
     case DNS_OPT_QUASILINEAR:
-      if (value != 0 && value != 1) return fail(h, DNS_E_INVALID, "quasi-linear is 0 or 1");
+      if (value < 0 || value > 2) return fail(h, DNS_E_INVALID, "quasi-linear is 0, 1 or 2 (adjoint)");
       if (value && h->advection != DNS_ADV_ADVECTIVE)
         return fail(h, DNS_E_INVALID, "the quasi-linear dynamics use the advective form");
-      h->quasilinear = value != 0;
+      h->quasilinear = int(value);
+      invalidate_graph(h);
+      return DNS_OK;
+    case DNS_OPT_FROZEN_MEAN:
+      if (value != 0 && value != 1) return fail(h, DNS_E_INVALID, "frozen mean is 0 or 1");
+      h->frozen_mean = value != 0;
       invalidate_graph(h);
       return DNS_OK;
     case DNS_OPT_MODE_TILE:
@@ -964,6 +974,140 @@ int dns_set_forcing(dns_handle* h, int member0, int count, const double* f_lapv,
     h->forcing_on = true;
     invalidate_graph(h);
   }
+  return DNS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Perturbation part (n_x >= 1 modes) of the members' states on the host, with
+// dv/dy = D1c v at every node, for energy inner products:
+//   <a, b> = (1/Ly) int dy sum_k m_k Re(u_a . conj u_b),
+//   |u|^2 + |w|^2 = (|dv/dy|^2 + |eta|^2) / k^2 per mode, m_k = 2 (n_x >= 1),
+// so that the kinetic energy density is E = <a, a> / 2.
+struct Perturbations {
+  int E = 0, K0 = 0, K = 0, N = 0, My = 0;
+  std::vector<double> v, eta, dv;  // device layout [K][N][E] (dv: [K][My][E]) complex
+  std::vector<double> k2;          // per mode
+};
+
+int load_perturbations(dns_handle* h, Perturbations* P) {
+  P->E = h->E;
+  P->K0 = h->NZ;  // first mode with n_x = 1
+  P->K = h->K;
+  P->N = h->N;
+  P->My = h->My;
+  const size_t n = size_t(h->K) * h->N * h->E * 2;
+  P->v.resize(n);
+  P->eta.resize(n);
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  HIP_OR_FAIL(h, hipMemcpy(P->v.data(), h->v, n * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(h, hipMemcpy(P->eta.data(), h->eta, n * sizeof(double), hipMemcpyDeviceToHost));
+  P->k2.assign(h->K, 1.0);
+  for (int m = 0; m < h->K; ++m) {
+    const int nx = m / h->NZ, iz = m - nx * h->NZ;
+    const int nz = iz < h->P ? iz : iz - h->NZ;
+    const double kx = h->kxs * nx, kz = h->kzs * nz;
+    if (nx > 0 || nz != 0) P->k2[m] = kx * kx + kz * kz;
+  }
+  P->dv.assign(size_t(h->K) * h->My * h->E * 2, 0.0);
+  const int E = h->E, N = h->N, My = h->My;
+  for (int m = P->K0; m < h->K; ++m)
+    for (int i = 0; i < My; ++i) {
+      double* d = &P->dv[(size_t(m) * My + i) * E * 2];
+      for (int j = 0; j < N; ++j) {
+        const double c = h->host_D1c[size_t(i) * N + j];
+        if (c == 0.0) continue;
+        const double* vv = &P->v[(size_t(m) * N + j) * E * 2];
+        for (int e = 0; e < 2 * E; ++e) d[e] += c * vv[e];
+      }
+    }
+  return DNS_OK;
+}
+
+double pert_inner(const dns_handle* h, const Perturbations& P, int a, int b) {
+  const int E = P.E, N = P.N, My = P.My;
+  const std::vector<double>& w = h->host_ccw;
+  double tot = 0.0;
+  for (int m = P.K0; m < P.K; ++m) {
+    double sv = 0.0, se = 0.0, sd = 0.0;
+    for (int j = 0; j < N; ++j) {
+      const size_t o = (size_t(m) * N + j) * E * 2;
+      sv += w[j + 1] * (P.v[o + 2 * a] * P.v[o + 2 * b] + P.v[o + 2 * a + 1] * P.v[o + 2 * b + 1]);
+      se += w[j + 1] * (P.eta[o + 2 * a] * P.eta[o + 2 * b] + P.eta[o + 2 * a + 1] * P.eta[o + 2 * b + 1]);
+    }
+    for (int i = 0; i < My; ++i) {
+      const size_t o = (size_t(m) * My + i) * E * 2;
+      sd += w[i] * (P.dv[o + 2 * a] * P.dv[o + 2 * b] + P.dv[o + 2 * a + 1] * P.dv[o + 2 * b + 1]);
+    }
+    tot += 2.0 * (sv + (sd + se) / P.k2[m]);
+  }
+  return tot / 2.0;  // 1 / Ly
+}
+
+// x_a -= c x_b (perturbation modes, v, eta and dv)
+void pert_axpy(Perturbations* P, int a, int b, double c) {
+  const int E = P->E;
+  auto upd = [&](std::vector<double>& x, size_t rows) {
+    for (size_t r = size_t(P->K0) * rows; r < size_t(P->K) * rows; ++r) {
+      double* row = &x[r * E * 2];
+      row[2 * a] -= c * row[2 * b];
+      row[2 * a + 1] -= c * row[2 * b + 1];
+    }
+  };
+  upd(P->v, P->N);
+  upd(P->eta, P->N);
+  upd(P->dv, P->My);
+}
+
+void pert_scale(Perturbations* P, int a, double c) {
+  const int E = P->E;
+  auto upd = [&](std::vector<double>& x, size_t rows) {
+    for (size_t r = size_t(P->K0) * rows; r < size_t(P->K) * rows; ++r) {
+      x[r * E * 2 + 2 * a] *= c;
+      x[r * E * 2 + 2 * a + 1] *= c;
+    }
+  };
+  upd(P->v, P->N);
+  upd(P->eta, P->N);
+  upd(P->dv, P->My);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dns_perturbation_energy(dns_handle* h, double* out) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) return fail(h, DNS_E_INVALID, "call on a group's handle");
+  if (!out) return fail(h, DNS_E_INVALID, "output is NULL");
+  Perturbations P;
+  const int rc = load_perturbations(h, &P);
+  if (rc) return rc;
+  for (int e = 0; e < h->E; ++e) out[e] = 0.5 * pert_inner(h, P, e, e);
+  return DNS_OK;
+}
+
+int dns_orthonormalize(dns_handle* h) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) return fail(h, DNS_E_INVALID, "call on a group's handle");
+  Perturbations P;
+  int rc = load_perturbations(h, &P);
+  if (rc) return rc;
+  for (int i = 0; i < h->E; ++i) {
+    for (int j = 0; j < i; ++j) pert_axpy(&P, i, j, 0.5 * pert_inner(h, P, i, j));  // <x_j, x_j> = 2
+    const double e = 0.5 * pert_inner(h, P, i, i);
+    if (!(e > 0.0) || !std::isfinite(e))
+      return fail(h, DNS_E_INVALID, "member " + std::to_string(i) + " has no independent perturbation");
+    pert_scale(&P, i, 1.0 / std::sqrt(e));
+  }
+  const size_t n = P.v.size();
+  HIP_OR_FAIL(h, hipMemcpy(h->v, P.v.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(h, hipMemcpy(h->eta, P.eta.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  h->vel_fresh = false;
   return DNS_OK;
 }
 

@@ -85,13 +85,15 @@ struct ModeArgs {
   int CRP, SR, TR;      // LDS geometry (mode_lds_geometry)
   double kxs, kzs, hdt, Ubot, Utop, Qtarget;
   int stage;      // 0, 1, 2: sub-step index; -1: velocities of the state only
+  int freeze_mean;  // 1: sub-steps leave the n_x = 0 modes and U, W untouched
   int poiseuille;
 };
 
 // Kernel launchers (kernels_*.hip).  Return hipSuccess or the launch error.
 // form 0: advective u . grad u; 1: rotational omega x u; 2: quasi-linear
-// advective (n_x >= 1 output linearised about the streamwise mean)
-constexpr int kPlaneForms = 3;
+// advective (n_x >= 1 output linearised about the streamwise mean); 3: adjoint
+// of the linearised advection
+constexpr int kPlaneForms = 4;
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s);
 // Chunk-row counts of the plane-kernel variants built for (precision, form,

@@ -183,6 +183,8 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   const int tile = flat - g * a.ntiles;
   const int nx = g / P, az = g - nx * P;
   const bool mean_group = (g == 0);
+  // a frozen streamwise mean: its groups keep their state and stage velocities
+  if (a.freeze_mean && nx == 0 && a.stage >= 0) return;
   VT* vel = static_cast<VT*>(a.vel);
   const VT* nl = static_cast<const VT*>(a.nl);
   const int s = a.stage;

@@ -40,6 +40,12 @@
 // (their row means vanish) beside the full products, and hands the forward
 // transform Lin_i + (row mean of the full product): its n_x = 0 mode is the
 // full advection's and every other mode is the linear term's.
+//
+// Adjoint form (kForm 3, optimal disturbances of a frozen mean): for a velocity
+// lambda' of the n_x >= 1 modes the term is -(U_m . grad) lambda' + (grad U_m)^T
+// lambda', i.e. Lin_i = -U_m dl_i/dx - W_m (dl_i/dz - <dl_i/dz>) - V_m (dl_i/dy -
+// <dl_i/dy>) plus, for i = y and z, sum_j lambda'_j <d u_j/dy> and sum_j
+// lambda'_j <d u_j/dz> (row means of the derivatives are those of the mean).
 #include <type_traits>
 
 #include "fft.h"
@@ -117,7 +123,7 @@ struct PlaneCfg {
 
 template <typename T, typename VT, int L, int P, int PP, int kForm>
 __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
-  constexpr bool kRot = kForm == 1, kQL = kForm == 2;
+  constexpr bool kRot = kForm == 1, kQL = kForm == 2 || kForm == 3, kAdj = kForm == 3;
   using C = cx<T>;
   using Cfg = PlaneCfg<T, L, P, PP>;
   constexpr int MX = Cfg::MX, MZ = Cfg::MZ, NZ = Cfg::NZ, R = Cfg::R, PH = Cfg::PH;
@@ -305,7 +311,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     } else {
     xinv(three, true, [&](int fi, int p, T val) {
       const T u = phys[PU][p];
-      if constexpr (kQL) lin[fi][p] = rmean[0][p / Cfg::MXP] * val;
+      if constexpr (kQL) lin[fi][p] = (kAdj ? -rmean[0][p / Cfg::MXP] : rmean[0][p / Cfg::MXP]) * val;
       if (fi == 0) {
         phys[PNU][p] = u * val;
         phys[PVY][p] = -val;
@@ -325,7 +331,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       if constexpr (kQL) {
         const int q = p / Cfg::MXP;
         const T Wm = rmean[2][q], Zm = rmean[3 + fi][q];
-        lin[fi][p] += Wm * (val - Zm) + (w - Wm) * Zm;
+        if constexpr (kAdj) lin[fi][p] -= Wm * (val - Zm);
+        else lin[fi][p] += Wm * (val - Zm) + (w - Wm) * Zm;
       }
       if (fi == 0) {
         phys[PNU][p] += w * val;
@@ -346,7 +353,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       if constexpr (kQL) {
         const int q = p / Cfg::MXP;
         const T Vm = rmean[1][q], Ym = rmean[6 + fi][q];
-        lin[fi == 0 ? 0 : 2][p] += Vm * (val - Ym) + (v - Vm) * Ym;
+        if constexpr (kAdj) lin[fi == 0 ? 0 : 2][p] -= Vm * (val - Ym);
+        else lin[fi == 0 ? 0 : 2][p] += Vm * (val - Ym) + (v - Vm) * Ym;
       }
       if (fi == 0) phys[PNU][p] += v * val; else phys[PNW][p] += v * val;
       if (want_stats) s_grad += double(val) * double(val);
@@ -359,7 +367,13 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       phys[PNV][p] += v * vy;
       if constexpr (kQL) {  // <dv/dy> = -<dw/dz> by continuity (<du/dx> = 0)
         const T Vm = rmean[1][q], Ym = -rmean[5][q];
-        lin[1][p] += Vm * (vy - Ym) + (v - Vm) * Ym;
+        if constexpr (kAdj) {
+          const T up = u - rmean[0][q], vp = v - Vm, wp = w - rmean[2][q];
+          lin[1][p] += -Vm * (vy - Ym) + up * rmean[6][q] + vp * Ym + wp * rmean[7][q];
+          lin[2][p] += up * rmean[3][q] + vp * rmean[4][q] + wp * rmean[5][q];
+        } else {
+          lin[1][p] += Vm * (vy - Ym) + (v - Vm) * Ym;
+        }
       }
       s_uv += double(u) * double(v);
       s_wv += double(w) * double(v);
@@ -499,7 +513,7 @@ constexpr bool variant_built() {
     return false;
   } else {
     using Cfg = PlaneCfg<T, L, L, PP>;
-    const size_t extra = Form == 2 ? (3 * Cfg::NPTS + 11 * PP) * sizeof(T) : 0;
+    const size_t extra = Form >= 2 ? (3 * Cfg::NPTS + 11 * PP) * sizeof(T) : 0;
     if (Cfg::kLdsBytes + extra > 160 * 1024) return false;
     for (int v = 0; v < 3; ++v)
       if ((sizeof(T) == 8 ? kVar64 : kVar32)[gi][v] == PP) return true;
@@ -545,6 +559,7 @@ const void* plane_fn_t(int form, int Nx, int pp) {
     case 0: return plane_fn_grid<T, 0>(Nx, pp);
     case 1: return plane_fn_grid<T, 1>(Nx, pp);
     case 2: return plane_fn_grid<T, 2>(Nx, pp);
+    case 3: return plane_fn_grid<T, 3>(Nx, pp);
   }
   return nullptr;
 }
@@ -603,7 +618,8 @@ int plane_variants(int precision, int form, int Nx, int* rows) {
 }
 
 // precision 0: FP64 storage and arithmetic; 1: FP32 storage and FFT arithmetic.
-// form 0: advective u . grad u; 1: rotational omega x u; 2: quasi-linear advective.
+// form 0: advective u . grad u; 1: rotational omega x u; 2: quasi-linear advective;
+// 3: adjoint of the quasi-linear advection.
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s) {
   if (!plane_supported(Nx, Nz) || form < 0 || form >= kPlaneForms) return hipErrorInvalidValue;

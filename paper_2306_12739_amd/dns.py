@@ -36,6 +36,7 @@ OPT_CHAINS = 7
 OPT_ADVECTION = 8
 OPT_SHARED_MEAN = 9
 OPT_QUASILINEAR = 10
+OPT_FROZEN_MEAN = 11
 
 ADV_ADVECTIVE = 0
 ADV_ROTATIONAL = 1
@@ -49,6 +50,7 @@ EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "d
             "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
             "dns_create_grouped", "dns_group_handle", "dns_tune",
             "dns_get_channels", "dns_set_channels", "dns_set_forcing",
+            "dns_perturbation_energy", "dns_orthonormalize",
             "sno_create", "sno_set_option", "sno_num_params", "sno_set_params", "sno_get_params",
             "sno_forward", "sno_loss_grad", "sno_train_step", "sno_sync", "sno_last_error",
             "sno_destroy"]
@@ -145,6 +147,8 @@ def library(path=LIB_PATH):
     lib.dns_get_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     lib.dns_set_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     lib.dns_set_forcing.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int]
+    lib.dns_perturbation_energy.argtypes = [vp, _DP]
+    lib.dns_orthonormalize.argtypes = [vp]
     lib.sno_create.argtypes = [ctypes.POINTER(SnoConfig), ctypes.c_ulonglong, ctypes.POINTER(vp)]
     lib.sno_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
     lib.sno_num_params.argtypes = [vp]
@@ -283,6 +287,14 @@ class Ensemble:
                 raise ValueError("forcing arrays do not match the grid")
         ptrs = [None if a is None else a.ctypes.data for a in arrs]
         return self._check(self.lib.dns_set_forcing(self.h, member0, count, ptrs[0], ptrs[1], 0))
+
+    def perturbation_energy(self):
+        out = np.zeros(self.E)
+        self._check(self.lib.dns_perturbation_energy(self.h, out.ctypes.data_as(_DP)))
+        return out
+
+    def orthonormalize(self):
+        return self._check(self.lib.dns_orthonormalize(self.h))
 
     def set_state_device(self, v, eta, U, W, member0=0):
         """torch device tensors (complex128 / float64, contiguous)."""
