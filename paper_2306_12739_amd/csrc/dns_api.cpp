@@ -987,9 +987,10 @@ namespace {
 //   |u|^2 + |w|^2 = (|dv/dy|^2 + |eta|^2) / k^2 per mode, m_k = 2 (n_x >= 1),
 // so that the kinetic energy density is E = <a, a> / 2.
 struct Perturbations {
-  int E = 0, K0 = 0, K = 0, N = 0, My = 0;
+  int E = 0, K0 = 0, K = 0, N = 0, My = 0, L = 0, NZ = 0;
   std::vector<double> v, eta, dv;  // device layout [K][N][E] (dv: [K][My][E]) complex
   std::vector<double> k2;          // per mode
+  std::vector<unsigned char> col;  // [E][L]: member has content in streamwise column n_x
 };
 
 int load_perturbations(dns_handle* h, Perturbations* P) {
@@ -1013,6 +1014,16 @@ int load_perturbations(dns_handle* h, Perturbations* P) {
   }
   P->dv.assign(size_t(h->K) * h->My * h->E * 2, 0.0);
   const int E = h->E, N = h->N, My = h->My;
+  P->L = h->L;
+  P->NZ = h->NZ;
+  P->col.assign(size_t(E) * h->L, 0);
+  for (int m = P->K0; m < h->K; ++m)
+    for (int j = 0; j < N; ++j)
+      for (int e = 0; e < E; ++e) {
+        const size_t o = ((size_t(m) * N + j) * E + e) * 2;
+        if (P->v[o] != 0.0 || P->v[o + 1] != 0.0 || P->eta[o] != 0.0 || P->eta[o + 1] != 0.0)
+          P->col[size_t(e) * h->L + m / h->NZ] = 1;
+      }
   for (int m = P->K0; m < h->K; ++m)
     for (int i = 0; i < My; ++i) {
       double* d = &P->dv[(size_t(m) * My + i) * E * 2];
@@ -1031,6 +1042,8 @@ double pert_inner(const dns_handle* h, const Perturbations& P, int a, int b) {
   const std::vector<double>& w = h->host_ccw;
   double tot = 0.0;
   for (int m = P.K0; m < P.K; ++m) {
+    const int nx = m / P.NZ;
+    if (!P.col[size_t(a) * P.L + nx] || !P.col[size_t(b) * P.L + nx]) continue;  // disjoint supports
     double sv = 0.0, se = 0.0, sd = 0.0;
     for (int j = 0; j < N; ++j) {
       const size_t o = (size_t(m) * N + j) * E * 2;
@@ -1059,6 +1072,7 @@ void pert_axpy(Perturbations* P, int a, int b, double c) {
   upd(P->v, P->N);
   upd(P->eta, P->N);
   upd(P->dv, P->My);
+  for (int nx = 0; nx < P->L; ++nx) P->col[size_t(a) * P->L + nx] |= P->col[size_t(b) * P->L + nx];
 }
 
 void pert_scale(Perturbations* P, int a, double c) {
@@ -1098,7 +1112,10 @@ int dns_orthonormalize(dns_handle* h) {
   int rc = load_perturbations(h, &P);
   if (rc) return rc;
   for (int i = 0; i < h->E; ++i) {
-    for (int j = 0; j < i; ++j) pert_axpy(&P, i, j, 0.5 * pert_inner(h, P, i, j));  // <x_j, x_j> = 2
+    for (int j = 0; j < i; ++j) {
+      const double c = 0.5 * pert_inner(h, P, i, j);  // <x_j, x_j> = 2
+      if (c != 0.0) pert_axpy(&P, i, j, c);
+    }
     const double e = 0.5 * pert_inner(h, P, i, i);
     if (!(e > 0.0) || !std::isfinite(e))
       return fail(h, DNS_E_INVALID, "member " + std::to_string(i) + " has no independent perturbation");
