@@ -162,7 +162,7 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 //   S  : solve stack [v0_e; F'_e; v0_o; F'_o] (interior halves), later eta (FH)
 //   S2 : solve stack [eta0_e; G'_e; eta0_o; G'_o], later dv/dy, u, dw/dy (FH)
 //   T  : Q = i kx N_u + i kz N_w (FH), later v (FH), later du/dy (FH)
-template <typename VT, bool kSplit>
+template <typename VT, bool kSplit, bool kForce>
 __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
         const int rowX = even ? kk : 2 * He + kk;
         double Fr = S[rowF * CRP + 2 * c], Fi = S[rowF * CRP + 2 * c + 1];
         double Gr = S2[rowF * CRP + 2 * c], Gi = S2[rowF * CRP + 2 * c + 1];
-        if (a.fv) {
+        if constexpr (kForce) {
           // external forcing held over the step enters every sub-step's terms
           // as F - f_lapv, G - f_eta (y-parity halves of the interior values)
           const size_t f1 = st(kk, c), f2 = st(N - 1 - kk, c);
@@ -744,37 +744,39 @@ int mode_member_tile(int My, int E) {
   return best;
 }
 
+namespace {
+template <bool kForce>
+const void* mode_fn(int precision) {
+  return precision == 0   ? reinterpret_cast<const void*>(&mode_kernel<double, false, kForce>)
+         : precision == 1 ? reinterpret_cast<const void*>(&mode_kernel<float, false, kForce>)
+                          : reinterpret_cast<const void*>(&mode_kernel<float, true, kForce>);
+}
+}  // namespace
+
 // Resolve the per-mode kernel instantiations on the current device.
 hipError_t mode_preload() {
-  const void* fns[3] = {reinterpret_cast<const void*>(&mode_kernel<double, false>),
-                        reinterpret_cast<const void*>(&mode_kernel<float, false>),
-                        reinterpret_cast<const void*>(&mode_kernel<float, true>)};
-  for (const void* fn : fns) {
-    hipFuncAttributes attr;
-    const hipError_t err = hipFuncGetAttributes(&attr, fn);
-    if (err != hipSuccess) return err;
+  for (int prec = 0; prec < 3; ++prec) {
+    for (const void* fn : {mode_fn<false>(prec), mode_fn<true>(prec)}) {
+      hipFuncAttributes attr;
+      const hipError_t err = hipFuncGetAttributes(&attr, fn);
+      if (err != hipSuccess) return err;
+    }
   }
   return hipSuccess;
 }
 
+// precision 0: FP64 stage buffers; 1: FP32 stage buffers; 2: FP32 stage
+// buffers and split-BF16 derivative products.  A forcing (a.fv) selects the
+// variant that subtracts it.
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   const int nblk = a.G * a.ntiles;
   const size_t lds = size_t(2 * a.SR + a.TR) * a.CRP * sizeof(double);
-  // precision 0: FP64 stage buffers; 1: FP32 stage buffers; 2: FP32 stage
-  // buffers and split-BF16 derivative contractions
-  const void* fn = precision == 0   ? reinterpret_cast<const void*>(&mode_kernel<double, false>)
-                   : precision == 1 ? reinterpret_cast<const void*>(&mode_kernel<float, false>)
-                                    : reinterpret_cast<const void*>(&mode_kernel<float, true>);
+  const void* fn = a.fv ? mode_fn<true>(precision) : mode_fn<false>(precision);
   hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (err != hipSuccess) return err;
-  if (precision == 0) {
-    hipLaunchKernelGGL((mode_kernel<double, false>), dim3(nblk), dim3(kNT), lds, s, a);
-  } else if (precision == 1) {
-    hipLaunchKernelGGL((mode_kernel<float, false>), dim3(nblk), dim3(kNT), lds, s, a);
-  } else {
-    hipLaunchKernelGGL((mode_kernel<float, true>), dim3(nblk), dim3(kNT), lds, s, a);
-  }
-  return hipGetLastError();
+  void* args[] = {const_cast<ModeArgs*>(&a)};
+  err = hipLaunchKernel(fn, dim3(nblk), dim3(kNT), args, lds, s);
+  return err != hipSuccess ? err : hipGetLastError();
 }
 
 }  // namespace dns
