@@ -48,6 +48,38 @@ class ModeOperators:
         self.A_eta = self.B_eta @ (I + c * lap)
 
 
+def kmm_v_operators(D1, D2, k2, c):
+    """A_v, B_v of the Helmholtz-Poisson (Kim-Moin-Moser) discretization of
+    the v equation: the same CN step (CN1) written for phi = Lap v,
+
+      [I - c Lap] phi_new = [I + c Lap] phi_0 - h dt F     (interior nodes)
+      Lap v_new = phi_new                                   (interior nodes)
+      v_new = 0, d v_new / dy = 0                           (walls)
+
+    with phi a polynomial on all My nodes (its wall values are the unknowns
+    that the influence-matrix method determines) and phi_0 = Lap v_0 on all
+    nodes.  Solved here as one block system for (phi, v):
+      v_new = A_v v_0 - h dt B_v F.
+    Alternative to the clamped fourth-derivative operator of Sec. 2; both are
+    spectral discretizations of the same equation and converge to each other."""
+    My = D1.shape[0]
+    N = My - 2
+    lapf = D2 - k2 * np.eye(My)              # full-grid Laplacian
+    M = np.zeros((My + N, My + N))
+    # Helmholtz rows (interior): phi - c Lap phi
+    M[:N, :My] = np.eye(My)[1:-1] - c * lapf[1:-1]
+    # Poisson rows (interior): Lap v (v = 0 at the walls) - phi
+    M[N:2 * N, My:] = lapf[1:-1, 1:-1]
+    M[N:2 * N, :My] = -np.eye(My)[1:-1]
+    # clamped walls: d v / dy = 0
+    M[2 * N, My:] = D1[0, 1:-1]
+    M[2 * N + 1, My:] = D1[-1, 1:-1]
+    S = np.linalg.solve(M, np.eye(My + N)[:, :N])[My:]         # v_new per unit R
+    # R = [I + c Lap] Lap v_0 on the interior rows
+    Q = ((np.eye(My) + c * lapf) @ lapf[:, 1:-1])[1:-1]
+    return S @ Q, S
+
+
 class MeanOperators:
     """Operators for the (kx, kz) = (0, 0) profiles U00 and W00, Eqs. (CN3)-(CN4).
 
@@ -76,7 +108,9 @@ class MeanOperators:
 class OperatorSet:
     """All operators of one run: Chebyshev matrices and per-h CN operators."""
 
-    def __init__(self, grid, My, Re, dt, U_bottom, U_top):
+    def __init__(self, grid, My, Re, dt, U_bottom, U_top, v_discretization="clamped"):
+        if v_discretization not in ("clamped", "kmm"):
+            raise ValueError("v_discretization must be 'clamped' or 'kmm'")
         self.My = My
         self.N = My - 2
         self.y = nodes(My)
@@ -97,6 +131,9 @@ class OperatorSet:
                     k2 = grid.K2[ix, iz]
                     if k2 == 0.0:
                         continue
-                    per[(ix, iz)] = ModeOperators(self.D2D, self.D2c, self.D4c, k2, c)
+                    op = ModeOperators(self.D2D, self.D2c, self.D4c, k2, c)
+                    if v_discretization == "kmm":
+                        op.A_v, op.B_v = kmm_v_operators(self.D1, self.D2, k2, c)
+                    per[(ix, iz)] = op
             self.modes[h] = per
             self.mean[h] = MeanOperators(self.D2, c, h * dt, U_bottom, U_top)

@@ -28,7 +28,7 @@ class OracleDNS:
     """Plain FP64 reference of the ensemble step (Sec. 3)."""
 
     def __init__(self, flow, Re, Lx, Lz, Nx, Ny, Nz, ensemble, dt, Uw=1.0, flux=4.0 / 3.0,
-                 advection="convective"):
+                 advection="convective", v_discretization="clamped"):
         self.flow = COUETTE if flow in (0, "couette") else POISEUILLE
         if advection not in ("convective", "rotational"):
             raise ValueError("advection must be 'convective' or 'rotational'")
@@ -43,7 +43,8 @@ class OracleDNS:
         else:
             self.U_bottom, self.U_top = 0.0, 0.0
         self.Q_target = float(flux)
-        self.ops = OperatorSet(self.grid, Ny, self.Re, self.dt, self.U_bottom, self.U_top)
+        self.ops = OperatorSet(self.grid, Ny, self.Re, self.dt, self.U_bottom, self.U_top,
+                               v_discretization=v_discretization)
         self.ccw = clenshaw_curtis_weights(Ny)
         self.y = self.ops.y
         self._stack_operators()
