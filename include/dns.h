@@ -148,6 +148,18 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  W00 as they are (a base flow for linearised or
                                  adjoint perturbation dynamics, App. B).
                                  Default 0.                                     */
+#define DNS_OPT_V_DISCRETIZATION 12 /* value: DNS_VDISC_*; rebuilds the v operators
+                                 on the host (long double) and reloads them   */
+
+/* Wall-normal discretizations of the v equation (Eq. (CN1)).  The paper uses
+ * the fourth derivative of the clamped interpolant (Sec. 2).  The alternative
+ * writes the CN step for phi = Lap v as a Helmholtz problem and Lap v = phi as
+ * a Poisson problem, both collocated at the interior nodes, with phi's wall
+ * values fixed by the clamped conditions v = dv/dy = 0 (the influence-matrix
+ * method of Kim, Moin and Moser); both are spectral discretizations of the
+ * same equation and converge to each other as Ny grows. */
+#define DNS_VDISC_CLAMPED 0   /* clamped fourth-derivative operator (default)     */
+#define DNS_VDISC_KMM 1       /* Helmholtz-Poisson with an influence matrix       */
 #define DNS_MAX_CHAINS 4
 
 /* Advection forms.  The paper advances the momentum equation (Sec. 2) with the
@@ -336,7 +348,8 @@ int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms
 
 /* Host-side operator construction for verification; needs no GPU.
  * Builds on the host, in extended precision, exactly the operators dns_create
- * uploads for one sub-step fraction (h_index 0: h = 1/2, 1: h = 1), with
+ * uploads for one sub-step fraction (h_index 0: h = 1/2, 1: h = 1) and v
+ * discretization (DNS_VDISC_*; A_v, B_v only depend on it), with
  * c = h dt / (2 Re) (Sec. 3.2, Eqs. (CN1)-(CN4), Listings 1 and 3):
  *   ops      : double [Nx/2 * Nz/2][4][Ny-2][Ny-2], row-major; per group
  *              g = n_x*(Nz/2) + |n_z| the folded A_v, B_v, A_eta, B_eta with
@@ -350,8 +363,8 @@ int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms
  *   ccw      : double [Ny] Clenshaw-Curtis weights.
  * NULL outputs are skipped.  Errors: DNS_E_INVALID, DNS_E_UNSUPPORTED. */
 int dns_host_operators(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, double dt,
-                       int h_index, double* ops, double* mean_ops, double* lift, double* green,
-                       double* D1, double* D1c, double* ccw);
+                       int h_index, int v_discretization, double* ops, double* mean_ops, double* lift,
+                       double* green, double* D1, double* D1c, double* ccw);
 
 #ifdef __cplusplus
 }

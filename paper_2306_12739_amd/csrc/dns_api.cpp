@@ -68,6 +68,7 @@ struct dns_handle {
   bool shared_mean = false;
   int quasilinear = 0;        // 0 full advection, 1 linearised, 2 adjoint of the linearised
   bool frozen_mean = false;   // sub-steps leave the n_x = 0 modes and U, W untouched
+  int v_discretization = DNS_VDISC_CLAMPED;
   std::vector<double> host_D1c, host_ccw;  // for energy inner products on the host
   bool forcing_on = false;
   double *fv = nullptr, *feta = nullptr;
@@ -235,6 +236,38 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   a.freeze_mean = h->frozen_mean ? 1 : 0;
   a.poiseuille = h->flow == DNS_FLOW_POISEUILLE;
   return a;
+}
+
+// [A | B] of N x N operators restricted to one y parity (n x 2n, n = ceil(N/2)
+// even or floor(N/2) odd), tiled for the FP64 MFMA.
+std::vector<double> parity_pair_block(const double* A, const double* B, int N, bool even) {
+  const int n = even ? (N + 1) / 2 : N / 2;
+  const std::vector<double> a = half_block(A, n, N, N, even);
+  const std::vector<double> b = half_block(B, n, N, N, even);
+  std::vector<double> cat(size_t(n) * 2 * n);
+  for (int r = 0; r < n; ++r)
+    for (int k = 0; k < n; ++k) {
+      cat[size_t(r) * 2 * n + k] = a[size_t(r) * n + k];
+      cat[size_t(r) * 2 * n + n + k] = b[size_t(r) * n + k];
+    }
+  return tile_for_mfma(cat.data(), n, 2 * n, 2 * n);
+}
+
+// Every fluctuation group's [A_v|B_v] (even, odd) then [A_eta|B_eta] (even,
+// odd) for sub-step fraction index hi, in the layout of dns_handle::opsT.
+std::vector<double> tile_group_operators(const HostOperators& ho, int hi, int N, int G, size_t stride) {
+  const size_t nn = size_t(N) * N;
+  std::vector<double> out(size_t(G) * stride, 0.0);
+  for (int g = 1; g < G; ++g) {
+    const double* base = ho.ops[hi].data() + size_t(g) * 4 * nn;
+    auto dst = out.begin() + size_t(g) * stride;
+    for (int blk = 0; blk < 4; ++blk) {  // v even, v odd, eta even, eta odd
+      const double* A = base + (blk < 2 ? 0 : 2 * nn);
+      const std::vector<double> t = parity_pair_block(A, A + nn, N, (blk & 1) == 0);
+      dst = std::copy(t.begin(), t.end(), dst);
+    }
+  }
+  return out;
 }
 
 // walls = false leaves out the two wall planes.  There, no-slip (v = 0 and u,
@@ -572,19 +605,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   auto ntile = [](int r, int k) { return size_t((r + 15) / 16) * ((k + 3) / 4) * 64; };
   const size_t per_e = ntile(He, 2 * He), per_o = ntile(Ho, 2 * Ho);
   h->op_group_stride = 2 * (per_e + per_o);
-  // [A | B] restricted to one parity (n x 2n), tiled
-  auto pair_block = [&](const double* A, const double* B, bool even) {
-    const int n = even ? He : Ho;
-    const std::vector<double> a = half_block(A, n, N, N, even);
-    const std::vector<double> b = half_block(B, n, N, N, even);
-    std::vector<double> cat(size_t(n) * 2 * n);
-    for (int r = 0; r < n; ++r)
-      for (int k = 0; k < n; ++k) {
-        cat[size_t(r) * 2 * n + k] = a[size_t(r) * n + k];
-        cat[size_t(r) * 2 * n + n + k] = b[size_t(r) * n + k];
-      }
-    return tile_for_mfma(cat.data(), n, 2 * n, 2 * n);
-  };
+  auto pair_block = [&](const double* A, const double* B, bool even) { return parity_pair_block(A, B, N, even); };
   // halves of an interior vector: even (He) then odd (Ho)
   auto halves = [&](const std::vector<double>& x) {
     std::vector<double> out(size_t(N), 0.0);
@@ -595,16 +616,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   std::vector<double> opsT[2], meanT[2], lift_h[2], green_h[2];
   const size_t nn = size_t(N) * N;
   for (int hi = 0; hi < 2; ++hi) {
-    opsT[hi].assign(size_t(h->G) * h->op_group_stride, 0.0);
-    for (int g = 1; g < h->G; ++g) {
-      const double* base = ho.ops[hi].data() + size_t(g) * 4 * nn;
-      auto dst = opsT[hi].begin() + size_t(g) * h->op_group_stride;
-      for (int blk = 0; blk < 4; ++blk) {  // v even, v odd, eta even, eta odd
-        const double* A = base + (blk < 2 ? 0 : 2 * nn);
-        const std::vector<double> t = pair_block(A, A + nn, (blk & 1) == 0);
-        dst = std::copy(t.begin(), t.end(), dst);
-      }
-    }
+    opsT[hi] = tile_group_operators(ho, hi, N, h->G, h->op_group_stride);
     meanT[hi] = pair_block(ho.mean_ops[hi].data(), ho.mean_ops[hi].data() + nn, true);
     const std::vector<double> mo = pair_block(ho.mean_ops[hi].data(), ho.mean_ops[hi].data() + nn, false);
     meanT[hi].insert(meanT[hi].end(), mo.begin(), mo.end());
@@ -773,7 +785,8 @@ int dns_set_option(dns_handle* h, int key, long long value) {
   ORDER_AFTER_PARENT(h);
   if (h->grouped() && (key == DNS_OPT_PRECISION || key == DNS_OPT_STATS || key == DNS_OPT_CHAINS ||
                        key == DNS_OPT_ADVECTION || key == DNS_OPT_SHARED_MEAN ||
-                       key == DNS_OPT_QUASILINEAR || key == DNS_OPT_FROZEN_MEAN)) {
+                       key == DNS_OPT_QUASILINEAR || key == DNS_OPT_FROZEN_MEAN ||
+                       key == DNS_OPT_V_DISCRETIZATION)) {
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
     for (dns_handle* sh : h->sub) {
       const int rc = dns_set_option(sh, key, value);
@@ -859,6 +872,24 @@ int dns_set_option(dns_handle* h, int key, long long value) {
       h->quasilinear = int(value);
       invalidate_graph(h);
       return DNS_OK;
+    case DNS_OPT_V_DISCRETIZATION: {
+      if (value != DNS_VDISC_CLAMPED && value != DNS_VDISC_KMM)
+        return fail(h, DNS_E_INVALID, "unknown v discretization");
+      if (value == h->v_discretization) return DNS_OK;
+      HostOperators ho;
+      if (build_operators(h->My, h->L, h->P, h->kxs, h->kzs, h->Re, h->dt, h->Ubot, h->Utop, &ho,
+                          int(value)) != 0)
+        return fail(h, DNS_E_INVALID, "a Crank-Nicolson operator is singular");
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      for (int hi = 0; hi < 2; ++hi) {
+        const std::vector<double> t = tile_group_operators(ho, hi, h->N, h->G, h->op_group_stride);
+        HIP_OR_FAIL(h, hipMemcpy(h->opsT[hi], t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+      }
+      h->max_cond = ho.max_cond;
+      h->v_discretization = int(value);
+      invalidate_graph(h);
+      return DNS_OK;
+    }
     case DNS_OPT_FROZEN_MEAN:
       if (value != 0 && value != 1) return fail(h, DNS_E_INVALID, "frozen mean is 0 or 1");
       h->frozen_mean = value != 0;
@@ -1643,9 +1674,10 @@ int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms
 }
 
 int dns_host_operators(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, double dt,
-                       int h_index, double* ops, double* mean_ops, double* lift, double* green,
-                       double* D1, double* D1c, double* ccw) {
-  if (!g || !(g->Lx > 0) || !(g->Lz > 0) || !(Re > 0) || !(dt > 0) || (h_index != 0 && h_index != 1))
+                       int h_index, int v_discretization, double* ops, double* mean_ops, double* lift,
+                       double* green, double* D1, double* D1c, double* ccw) {
+  if (!g || !(g->Lx > 0) || !(g->Lz > 0) || !(Re > 0) || !(dt > 0) || (h_index != 0 && h_index != 1) ||
+      (v_discretization != DNS_VDISC_CLAMPED && v_discretization != DNS_VDISC_KMM))
     return fail(nullptr, DNS_E_INVALID, "invalid operator request");
   if (Nx <= 0 || Nz <= 0 || (Nx % 2) || (Nz % 2) || Ny < 5 || Ny > 257)
     return fail(nullptr, DNS_E_INVALID, "invalid grid");
@@ -1653,7 +1685,8 @@ int dns_host_operators(const dns_geometry* g, double Re, int Nx, int Ny, int Nz,
   const double Ub = g->flow == DNS_FLOW_COUETTE ? -Uw : 0.0;
   const double Ut = g->flow == DNS_FLOW_COUETTE ? Uw : 0.0;
   HostOperators ho;
-  if (build_operators(Ny, Nx / 2, Nz / 2, 2.0 * M_PI / g->Lx, 2.0 * M_PI / g->Lz, Re, dt, Ub, Ut, &ho))
+  if (build_operators(Ny, Nx / 2, Nz / 2, 2.0 * M_PI / g->Lx, 2.0 * M_PI / g->Lz, Re, dt, Ub, Ut, &ho,
+                      v_discretization))
     return fail(nullptr, DNS_E_INVALID, "a Crank-Nicolson operator is singular");
   auto put = [](double* dst, const std::vector<double>& src) {
     if (dst) std::memcpy(dst, src.data(), src.size() * sizeof(double));

@@ -176,9 +176,10 @@ struct HostOperators {
   std::vector<double> green[2];     // per h: N
   double max_cond = 0.0;
 };
-// h index 0 is h = 1/2, index 1 is h = 1.
+// h index 0 is h = 1/2, index 1 is h = 1.  v_discretization 0: clamped fourth-
+// derivative operator; 1: Helmholtz-Poisson system with clamped walls.
 int build_operators(int My, int L, int P, double kxs, double kzs, double Re, double dt,
-                    double Ubot, double Utop, HostOperators* out);
+                    double Ubot, double Utop, HostOperators* out, int v_discretization = 0);
 
 // ---- channel form of states (learned spin-up) -------------------------------------
 // cinv: Chebyshev coefficients from node values (My x My); tmat: node values

@@ -215,6 +215,66 @@ ld fold_pair(const Mat& lhs, const Mat& rhs, int n, double* A, double* B) {
   return inf_norm(lhs, n) * inf_norm(I, n);
 }
 
+// Helmholtz-Poisson (Kim-Moin-Moser) form of the v step: with phi = Lap v a
+// polynomial on all My nodes,
+//   [I - c Lap] phi_new = [I + c Lap] Lap v_0 - h dt F   (interior nodes)
+//   Lap v_new = phi_new                                   (interior nodes)
+//   v_new = 0 and d v_new/dy = 0                          (walls)
+// solved as one block system for (phi, v); A = S Q and B = S with S the
+// v-rows of its inverse on the Helmholtz right-hand side and Q = [I + c Lap]
+// Lap restricted to interior rows and columns.  Returns a lower-bound estimate
+// of cond_inf of the block matrix.
+ld kmm_pair(const Cheb& ch, ld k2, ld c, double* A, double* B) {
+  const int My = ch.My, N = ch.N, n = My + N;
+  Mat lapf(size_t(My) * My);
+  for (int i = 0; i < My; ++i)
+    for (int j = 0; j < My; ++j) lapf[size_t(i) * My + j] = ch.D2[size_t(i) * My + j] - (i == j ? k2 : 0.0L);
+  Mat M(size_t(n) * n, 0.0L);
+  for (int i = 0; i < N; ++i) {
+    const int r = i + 1;  // interior node
+    for (int j = 0; j < My; ++j) {
+      M[size_t(i) * n + j] = (r == j ? 1.0L : 0.0L) - c * lapf[size_t(r) * My + j];  // Helmholtz
+    }
+    M[size_t(N + i) * n + r] = -1.0L;                                                   // Poisson: -phi
+    for (int j = 0; j < N; ++j) M[size_t(N + i) * n + My + j] = lapf[size_t(r) * My + j + 1];
+  }
+  for (int j = 0; j < N; ++j) {
+    M[size_t(2 * N) * n + My + j] = ch.D1[size_t(0) * My + j + 1];
+    M[size_t(2 * N + 1) * n + My + j] = ch.D1[size_t(My - 1) * My + j + 1];
+  }
+  Mat LU = M;
+  std::vector<int> piv;
+  if (!lu_factor(LU, piv, n)) return INFINITY;
+  Mat X(size_t(n) * N, 0.0L);  // columns: unit right-hand sides of the Helmholtz rows
+  for (int i = 0; i < N; ++i) X[size_t(i) * N + i] = 1.0L;
+  lu_solve(LU, piv, n, X, N);
+  // Q = ([I + c Lap] Lap[:, interior])[interior rows]
+  Mat Q(size_t(N) * N, 0.0L);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const int r = i + 1;
+      ld q = lapf[size_t(r) * My + j + 1];
+      for (int m = 0; m < My; ++m) q += c * lapf[size_t(r) * My + m] * lapf[size_t(m) * My + j + 1];
+      Q[size_t(i) * N + j] = q;
+    }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      ld a = 0.0L;
+      for (int m = 0; m < N; ++m) a += X[size_t(My + i) * N + m] * Q[size_t(m) * N + j];
+      A[size_t(i) * N + j] = double(a);
+      B[size_t(i) * N + j] = double(X[size_t(My + i) * N + j]);
+    }
+  // conditioning estimate from the inverse columns already at hand (a lower
+  // bound of cond_inf(M); a full inverse would cost n^3 per mode)
+  ld xmax = 0.0L;
+  for (int i = 0; i < n; ++i) {
+    ld row = 0.0L;
+    for (int j = 0; j < N; ++j) row += std::fabs(X[size_t(i) * N + j]);
+    xmax = std::max(xmax, row);
+  }
+  return inf_norm(M, n) * xmax;
+}
+
 }  // namespace
 
 std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm) {
@@ -279,7 +339,7 @@ std::vector<double> half_block(const double* M, int rows_out, int Cn, int ldm, b
 }
 
 int build_operators(int My, int L, int P, double kxs, double kzs, double Re, double dt, double Ubot,
-                    double Utop, HostOperators* out) {
+                    double Utop, HostOperators* out, int v_discretization) {
   Cheb ch;
   build_cheb(My, &ch);
   const int N = My - 2;
@@ -346,7 +406,8 @@ int build_operators(int My, int L, int P, double kxs, double kzs, double Re, dou
             rhe[ij] = id + c * lap;
           }
         double* base = out->ops[hi].data() + size_t(g) * 4 * N * N;
-        const ld cv = fold_pair(lhs, rhs, N, base, base + size_t(N) * N);
+        const ld cv = v_discretization == 1 ? kmm_pair(ch, k2, c, base, base + size_t(N) * N)
+                                            : fold_pair(lhs, rhs, N, base, base + size_t(N) * N);
         const ld ce = fold_pair(lhe, rhe, N, base + size_t(2) * N * N, base + size_t(3) * N * N);
         conds[size_t(hi) * G + g] = std::max(cv, ce);
       }

@@ -37,6 +37,10 @@ OPT_ADVECTION = 8
 OPT_SHARED_MEAN = 9
 OPT_QUASILINEAR = 10
 OPT_FROZEN_MEAN = 11
+OPT_V_DISCRETIZATION = 12
+
+VDISC_CLAMPED = 0
+VDISC_KMM = 1
 
 ADV_ADVECTIVE = 0
 ADV_ROTATIONAL = 1
@@ -166,7 +170,7 @@ def library(path=LIB_PATH):
     lib.sno_destroy.restype = None
     lib.dns_host_operators.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                       _DP, _DP, _DP, _DP, _DP, _DP, _DP]
+                                       ctypes.c_int, _DP, _DP, _DP, _DP, _DP, _DP, _DP]
     for name in EXPORTED:
         if name not in ("dns_destroy", "dns_last_error", "sno_destroy", "sno_last_error",
                         "sno_num_params"):
@@ -175,7 +179,7 @@ def library(path=LIB_PATH):
     return lib
 
 
-def host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, h_index, Uw=1.0):
+def host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, h_index, Uw=1.0, v_discretization=0):
     """Operators as built by the library's host builder (no GPU needed)."""
     lib = library()
     N = Ny - 2
@@ -184,7 +188,7 @@ def host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, h_index, Uw=1.0):
            "green": np.zeros(N), "D1": np.zeros((Ny, Ny)), "D1c": np.zeros((Ny, N)),
            "ccw": np.zeros(Ny)}
     g = Geometry(flow, Lx, Lz, Uw, 0.0)
-    rc = lib.dns_host_operators(ctypes.byref(g), Re, Nx, Ny, Nz, dt, h_index,
+    rc = lib.dns_host_operators(ctypes.byref(g), Re, Nx, Ny, Nz, dt, h_index, v_discretization,
                                 *[_ptr(out[k]) for k in ("ops", "mean_ops", "lift", "green",
                                                          "D1", "D1c", "ccw")])
     if rc != DNS_OK:

@@ -110,7 +110,7 @@ def test_ny_beyond_mode_lds_is_unsupported_without_gpu():
 
 def test_binding_constants_match_the_header():
     text = open(HEADERS[0]).read()
-    defs = dict(re.findall(r"#define DNS_((?:OPT|PREC|ADV)_[A-Z0-9_]+)\s+(-?\d+)", text))
+    defs = dict(re.findall(r"#define DNS_((?:OPT|PREC|ADV|VDISC)_[A-Z0-9_]+)\s+(-?\d+)", text))
     assert {"OPT_ADVECTION", "ADV_ADVECTIVE", "ADV_ROTATIONAL"} <= set(defs)
     for name, value in defs.items():
         assert getattr(dns, name) == int(value), name

@@ -48,3 +48,29 @@ def test_host_operators_match_oracle(case, h_index):
             # the -n_z partner shares the operators
             assert np.array_equal(o.modes[h][(ix, g.conj_iz[az] if az else 0)].A_v, op.A_v) or az == 0
     assert worst <= 1e-11, worst
+
+
+@pytest.mark.parametrize("case", CASES, ids=["couette-33", "channel-49"])
+def test_host_kmm_operators_match_oracle(case):
+    """The Helmholtz-Poisson v operators: long-double block solve of the library
+    against the oracle's FP64 block solve (A_eta, B_eta are unchanged)."""
+    flow, Re, Lx, Lz, Nx, Ny, Nz, dt = case
+    lib_ops = dns.host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, 1, v_discretization=dns.VDISC_KMM)
+    base = dns.host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, 1)
+    sim = oracle.OracleDNS(flow, Re, Lx, Lz, Nx, Ny, Nz, 1, dt, v_discretization="kmm")
+    P = Nz // 2
+    worst = 0.0
+    for ix in range(Nx // 2):
+        for az in range(P):
+            if ix == 0 and az == 0:
+                continue
+            op = sim.ops.modes[1.0][(ix, az)]
+            got = lib_ops["ops"][ix * P + az]
+            for q, ref in enumerate((op.A_v, op.B_v)):
+                worst = max(worst, np.abs(got[q] - ref).max() / np.abs(ref).max())
+            assert np.array_equal(got[2], base["ops"][ix * P + az][2])
+            # a different matrix from the clamped operator (they differ most on the
+            # stiff, unresolved modes, where CN factors approach -1)
+            d = np.abs(got[0] - base["ops"][ix * P + az][0]).max() / np.abs(got[0]).max()
+            assert d > 1e-14
+    assert worst <= 1e-10, worst
