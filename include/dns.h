@@ -61,7 +61,7 @@ typedef struct {
 
 /* Create an ensemble solver (Sec. 3.2: operators are built once per (kx,kz) and
  * h in {1/2, 1}, on the host in extended precision, then uploaded).
- *   Nx, Nz : 16, 32, 48 or 64 with Nx == Nz;  Ny : 5..252 (odd or even);
+ *   Nx, Nz : 16, 32, 48, 64 or 72 with Nx == Nz;  Ny : 5..252 (odd or even);
  *   ensemble >= 1; dt > 0; Re > 0.
  * The state is initialised to the laminar profile (Couette U = Uw y, channel
  * U = 1 - y^2) with zero perturbations.  Device memory is owned by the handle.

@@ -295,6 +295,12 @@ PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool wal
 
 // plane-kernel form: 0 advective, 1 rotational, 2 quasi-linear advective
 int plane_form(const dns_handle* h) { return h->quasilinear ? 1 + h->quasilinear : h->advection; }
+// some (form, precision) pairs have no chunk variant within the LDS of the larger grids
+bool form_fits(const dns_handle* h, int precision, int form) {
+  int rows[3];
+  return plane_variants(precision == DNS_PREC_FP64 ? 0 : 1, form, h->Nx, rows) > 0;
+}
+
 int& plane_var(dns_handle* h) { return h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1][plane_form(h)]; }
 
 hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr,
@@ -528,7 +534,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   if (dc == DNS_E_INVALID)
     return fail(nullptr, dc, "need even Nx, Nz > 0, 5 <= Ny <= 257 and ensemble >= 1");
   if (dc == DNS_E_UNSUPPORTED)
-    return fail(nullptr, dc, "grid not built: Nx == Nz in {16, 32, 48, 64} are supported");
+    return fail(nullptr, dc, "grid not built: Nx == Nz in {16, 32, 48, 64, 72} are supported");
   {
     // one member per per-mode workgroup must fit the workgroup LDS (Ny <= 252)
     int crp, sr, tr;
@@ -799,6 +805,8 @@ int dns_set_option(dns_handle* h, int key, long long value) {
     case DNS_OPT_PRECISION:
       if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32 && value != DNS_PREC_MIXED_3XBF16)
         return fail(h, DNS_E_INVALID, "unknown precision");
+      if (!form_fits(h, int(value), plane_form(h)))
+        return fail(h, DNS_E_UNSUPPORTED, "no advection-kernel variant of this form fits this grid at that precision");
       if (value != h->precision) {
         h->precision = int(value);
         h->vel_fresh = false;
@@ -869,6 +877,8 @@ int dns_set_option(dns_handle* h, int key, long long value) {
       if (value < 0 || value > 2) return fail(h, DNS_E_INVALID, "quasi-linear is 0, 1 or 2 (adjoint)");
       if (value && h->advection != DNS_ADV_ADVECTIVE)
         return fail(h, DNS_E_INVALID, "the quasi-linear dynamics use the advective form");
+      if (!form_fits(h, h->precision, value ? 1 + int(value) : h->advection))
+        return fail(h, DNS_E_UNSUPPORTED, "no quasi-linear advection-kernel variant fits this grid at this precision");
       h->quasilinear = int(value);
       invalidate_graph(h);
       return DNS_OK;

@@ -161,13 +161,16 @@ struct Split;
 template <> struct Split<8> { static constexpr int A = 2, B = 4; };
 template <> struct Split<12> { static constexpr int A = 3, B = 4; };
 template <> struct Split<16> { static constexpr int A = 4, B = 4; };
+template <> struct Split<18> { static constexpr int A = 2, B = 9; };
 template <> struct Split<24> { static constexpr int A = 4, B = 6; };
 template <> struct Split<32> { static constexpr int A = 4, B = 8; };
 template <> struct Split<36> { static constexpr int A = 6, B = 6; };
 template <> struct Split<48> { static constexpr int A = 6, B = 8; };
+template <> struct Split<54> { static constexpr int A = 6, B = 9; };
 template <> struct Split<64> { static constexpr int A = 8, B = 8; };
 template <> struct Split<72> { static constexpr int A = 8, B = 9; };
 template <> struct Split<96> { static constexpr int A = 8, B = 12; };
+template <> struct Split<108> { static constexpr int A = 12, B = 9; };
 template <> struct Split<144> { static constexpr int A = 12, B = 12; };
 
 // Batched length-N transform, sign DIR, over NBATCH independent sequences,

@@ -502,13 +502,15 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
 // default, the others are candidates for the tuner.  Every variant keeps the
 // workgroup's LDS within 160 KB.
 namespace {
-constexpr int kVar64[4][3] = {{24, 12, 8}, {16, 24, 8}, {12, 8, 0}, {16, 12, 8}};
-constexpr int kVar32[4][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 16}};
-int grid_index(int Nx) { return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : -1; }
+constexpr int kVar64[5][3] = {{24, 12, 8}, {16, 24, 8}, {12, 8, 0}, {16, 12, 8}, {18, 12, 0}};
+constexpr int kVar32[5][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 16}, {36, 18, 12}};
+int grid_index(int Nx) {
+  return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : Nx == 72 ? 4 : -1;
+}
 
 template <typename T, int L, int PP, int Form>
 constexpr bool variant_built() {
-  constexpr int gi = L == 8 ? 0 : L == 16 ? 1 : L == 24 ? 2 : L == 32 ? 3 : -1;
+  constexpr int gi = L == 8 ? 0 : L == 16 ? 1 : L == 24 ? 2 : L == 32 ? 3 : L == 36 ? 4 : -1;
   if constexpr (gi < 0 || (3 * L) % PP != 0) {
     return false;
   } else {
@@ -534,6 +536,7 @@ const void* plane_fn_rows(int pp) {
     case 8: return plane_fn_if_built<T, L, 8, Form>();
     case 12: return plane_fn_if_built<T, L, 12, Form>();
     case 16: return plane_fn_if_built<T, L, 16, Form>();
+    case 18: return plane_fn_if_built<T, L, 18, Form>();
     case 24: return plane_fn_if_built<T, L, 24, Form>();
     case 32: return plane_fn_if_built<T, L, 32, Form>();
     case 36: return plane_fn_if_built<T, L, 36, Form>();
@@ -549,6 +552,7 @@ const void* plane_fn_grid(int Nx, int pp) {
     case 32: return plane_fn_rows<T, 16, Form>(pp);
     case 48: return plane_fn_rows<T, 24, Form>(pp);
     case 64: return plane_fn_rows<T, 32, Form>(pp);
+    case 72: return plane_fn_rows<T, 36, Form>(pp);
   }
   return nullptr;
 }
@@ -582,7 +586,7 @@ int table_rows(int precision, int Nx, int* rows) {
 }  // namespace
 
 bool plane_supported(int Nx, int Nz) {
-  return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64);
+  return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64 || Nx == 72);
 }
 
 // Resolve every built plane-kernel variant of grid Nx (both precisions, every
@@ -592,8 +596,7 @@ hipError_t plane_preload(int Nx) {
   for (int prec = 0; prec < 2; ++prec) {
     for (int form = 0; form < kPlaneForms; ++form) {
       int rows[3];
-      const int n = plane_variants(prec, form, Nx, rows);
-      if (n == 0) return hipErrorInvalidValue;
+      const int n = plane_variants(prec, form, Nx, rows);  // 0: this form does not fit this grid
       for (int v = 0; v < n; ++v) {
         const void* fn = plane_fn(prec, form, Nx, rows[v]);
         if (!fn) return hipErrorInvalidValue;

@@ -206,6 +206,22 @@ def test_parity_channel_64x97x64_sampled_members():
     gpu.close()
 
 
+def test_parity_channel_72x73x72_fp64():
+    """The 72-mode grid (3/2 grid of 108 points, radix 12 x 9 transforms)."""
+    say("case: channel 72x73x72 E=2 FP64, 3 steps dt=0.008")
+    st = inputs.random_state(1, 2 * np.pi, np.pi, 72, 73, 72, 2, 0.3, 61, spectrum="k2")
+    gpu, ref = make_pair(1, 4200.0, 2 * np.pi, np.pi, 72, 73, 72, 2, 0.008, st)
+    gpu.step(3)
+    ref.step(3)
+    errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
+    say("errors:", errs)
+    for k, e in errs.items():
+        assert e <= 1e-10, (k, e)
+    with pytest.raises(dns.DnsError):        # no FP64 quasi-linear variant fits this grid
+        gpu.set_option(dns.OPT_QUASILINEAR, 1)
+    gpu.close()
+
+
 @pytest.mark.parametrize("flow", [0, 1])
 def test_laminar_fixed_point_gpu(flow):
     say(f"case: laminar fixed point flow={flow}")

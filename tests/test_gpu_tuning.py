@@ -21,10 +21,12 @@ GRIDS = [  # (flow, Re, Lx, Lz, N, Ny, dt, amplitude)
     (0, 600.0, 1.75 * np.pi, 1.2 * np.pi, 32, 49, 0.02, 0.2),
     (0, 1000.0, 1.75 * np.pi, 1.2 * np.pi, 48, 65, 0.02, 0.2),
     (1, 4200.0, 2.0 * np.pi, np.pi, 64, 97, 0.005, 0.3),
+    (1, 4200.0, 2.0 * np.pi, np.pi, 72, 73, 0.005, 0.3),
 ]
 ROWS = {  # built variants, default first
-    dns.PREC_FP64: {16: [24, 12, 8], 32: [16, 24, 8], 48: [12, 8], 64: [16, 12, 8]},
-    dns.PREC_MIXED_FP32: {16: [24, 12, 8], 32: [16, 24, 48], 48: [12, 24, 36], 64: [32, 24, 16]},
+    dns.PREC_FP64: {16: [24, 12, 8], 32: [16, 24, 8], 48: [12, 8], 64: [16, 12, 8], 72: [12]},
+    dns.PREC_MIXED_FP32: {16: [24, 12, 8], 32: [16, 24, 48], 48: [12, 24, 36], 64: [32, 24, 16],
+                          72: [18, 12]},
 }
 
 
