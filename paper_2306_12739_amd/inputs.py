@@ -109,6 +109,13 @@ WORKLOADS = {
     "channel-re4200-64x97x64-e16": dict(
         flow=1, Re=4200.0, Lx=2.0 * np.pi, Lz=np.pi, Nx=64, Ny=97, Nz=64,
         ensemble=16, dt=0.005, steps=1000, amplitude=0.3, spectrum="k2", seed=1002),
+    # paper-resolution grids (72 x 73 x 72 on the 108 x 73 x 108 grid), box 2 pi x 2 x pi, dt = 0.008
+    "channel-re4200-72x73x72-e16": dict(
+        flow=1, Re=4200.0, Lx=2.0 * np.pi, Lz=np.pi, Nx=72, Ny=73, Nz=72,
+        ensemble=16, dt=0.008, steps=50000, amplitude=0.3, spectrum="k2", seed=1008),
+    "couette-re3000-72x73x72-e16": dict(
+        flow=0, Re=3000.0, Lx=2.0 * np.pi, Lz=np.pi, Nx=72, Ny=73, Nz=72,
+        ensemble=16, dt=0.008, steps=50000, amplitude=0.3, spectrum="k2", seed=1009),
 }
 
 
