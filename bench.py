@@ -62,8 +62,10 @@ def kernel_model(w, E, precision, form="advective"):
     Mx, Mz = 3 * L, 3 * P
     vt = 8 if precision == "fp64" else 4
     cplx = 2 * vt
-    # advection kernel: read u,v,w,uy,wy spectra, write Nu,Nv,Nw spectra, plane means
-    plane_bytes = (5 + 3) * My * K * E * cplx + 2 * My * E * 8
+    # advection kernel, in the launch shape of a step (the My - 2 interior
+    # planes): read u,v,w,uy,wy spectra, write Nu,Nv,Nw spectra, plane means
+    Mp = My - 2
+    plane_bytes = (5 + 3) * Mp * K * E * cplx + 2 * Mp * E * 8
     # flops: complex FFT 5 n log2 n, real FFT 2.5 n log2 n (conventional counts);
     # advective form: 8 z- and 11 x-inverses, u.grad u and the means; rotational
     # form: 6 and 6, omega x u and the means
@@ -73,7 +75,7 @@ def kernel_model(w, E, precision, form="advective"):
     prod = Mx * Mz * pw
     xfwd = 3 * Mz * 2.5 * Mx * np.log2(Mx)
     zfwd = 3 * L * 5 * Mz * np.log2(Mz)
-    plane_flops = (zinv + xinv + prod + xfwd + zfwd) * My * E
+    plane_flops = (zinv + xinv + prod + xfwd + zfwd) * Mp * E
     # per-(kx,kz) kernel (second sub-step): N spectra in, velocity spectra out,
     # state in and history in/out in FP64, and the y-parity halves of
     # [A_v | B_v] and [A_eta | B_eta] once per group

@@ -272,9 +272,10 @@ std::vector<double> tile_group_operators(const HostOperators& ho, int hi, int N,
 
 // walls = false leaves out the two wall planes.  There, no-slip (v = 0 and u,
 // w uniform in x-z) makes the plane means and the terms N_u, N_w vanish
-// exactly in both advection forms; N_v at a wall (zero in the advective form,
-// -u du/dy in the rotational one) enters no interior equation.  Their
-// statistics sums are still needed, so a launch with sums keeps them.
+// exactly in every advection form; N_v at a wall (zero in the advective form,
+// -u du/dy in the rotational one) enters no interior equation.  Steps never
+// visit them (the stage buffers start zeroed) and take their statistics sums
+// from launch_wall_sums.
 PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool walls = true) {
   PlaneArgs a{};
   a.e0 = e0;
@@ -306,7 +307,7 @@ int& plane_var(dns_handle* h) { return h->plane_var[h->precision == DNS_PREC_FP6
 hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipStream_t st = nullptr,
                         bool walls = true) {
   return launch_plane(h->precision, plane_form(h), h->Nx, h->Nz, plane_var(h),
-                      plane_args(h, sums, e0, ec, walls || sums), st ? st : h->stream);
+                      plane_args(h, sums, e0, ec, walls), st ? st : h->stream);
 }
 
 // Members per mode-kernel workgroup: 1, 2, 4 or 8, at most the ensemble size
@@ -379,9 +380,12 @@ int set_chains(dns_handle* h, int n) {
 // One step of members [e0, e0 + ec) on stream st.
 int enqueue_members(dns_handle* h, int e0, int ec, hipStream_t st) {
   for (int s = 0; s < 3; ++s) {
-    // the first sub-step writes the wall-plane terms that the later sub-steps
-    // of the step then reuse (the solves read only their exact zeros)
-    HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st, s == 0));
+    // the wall planes' advection terms and means are exact zeros (the buffers
+    // start zeroed); their statistics sums come from the spectral fields
+    HIP_OR_FAIL(h, plane_launch(h, s == 0, e0, ec, st, false));
+    if (s == 0)
+      HIP_OR_FAIL(h, launch_wall_sums(h->precision == DNS_PREC_FP64 ? 0 : 1, h->vel, h->psum, h->means, h->My,
+                                      h->E, h->K, h->NZ, h->P, h->kxs, h->kzs, e0, ec < 0 ? h->E : ec, st));
     if (h->shared_mean)  // one chain holds every member (set_chains)
       HIP_OR_FAIL(h, launch_member_mean(h->precision == DNS_PREC_FP64 ? 0 : 1, h->nl, h->means, h->My, h->E,
                                         h->K, h->NZ, st));
@@ -732,6 +736,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   ok &= hipMemset(h->divmax, 0, h->E * sizeof(unsigned long long)) == hipSuccess;
   ok &= hipMemset(h->acc, 0, (size_t(NPA) * MyE + 2 * h->E) * sizeof(double)) == hipSuccess;
   ok &= hipMemset(h->means, 0, 2 * MyE * sizeof(double)) == hipSuccess;
+  ok &= hipMemset(h->nl, 0, size_t(3) * h->My * h->K * h->E * 2 * vt_size(DNS_PREC_FP64)) == hipSuccess;
   ok &= hipMemset(h->psum, 0, size_t(NPS) * MyE * sizeof(double)) == hipSuccess;
   if (!ok) return fail_free(DNS_E_HIP, "uploading operators / initial state failed");
   if (hipDeviceSynchronize() != hipSuccess) return fail_free(DNS_E_HIP, "hipDeviceSynchronize");
@@ -1509,7 +1514,7 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
   for (int v = 0; v < nv; ++v) {
     plane_var(h) = v;
     double ms;
-    const int rc = time_launches(h, kReps, [&] { return plane_launch(h, false); }, &ms);
+    const int rc = time_launches(h, kReps, [&] { return plane_launch(h, false, 0, -1, nullptr, false); }, &ms);
     if (rc) return rc;
     if (ms < best_p) best_p = ms, best_v = v;
   }
@@ -1660,12 +1665,13 @@ int dns_kernel_times(dns_handle* h, int nreps, double* plane_ms, double* mode_ms
   HIP_OR_FAIL(h, hipEventCreate(&e0));
   HIP_OR_FAIL(h, hipEventCreate(&e1));
   HIP_OR_FAIL(h, hipEventCreate(&e2));
-  // one untimed launch of each, then nreps timed launches of each
-  HIP_OR_FAIL(h, plane_launch(h, false));
+  // one untimed launch of each, then nreps timed launches of each, in the
+  // launch shape of a step (interior planes, all members)
+  HIP_OR_FAIL(h, plane_launch(h, false, 0, -1, nullptr, false));
   HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, 1), h->stream));
   HIP_OR_FAIL(h, hipEventRecord(e0, h->stream));
   for (int r = 0; r < nreps; ++r)
-    HIP_OR_FAIL(h, plane_launch(h, false));
+    HIP_OR_FAIL(h, plane_launch(h, false, 0, -1, nullptr, false));
   HIP_OR_FAIL(h, hipEventRecord(e1, h->stream));
   for (int r = 0; r < nreps; ++r) HIP_OR_FAIL(h, launch_mode(h->precision, mode_args(h, 1), h->stream));
   HIP_OR_FAIL(h, hipEventRecord(e2, h->stream));

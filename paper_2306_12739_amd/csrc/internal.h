@@ -126,6 +126,11 @@ std::vector<double> tile_for_mfma(const double* M, int R, int Kd, int ldm);
 // i < rows_out are the first-half rows of M.
 std::vector<double> half_block(const double* M, int rows_out, int Cn, int ldm, bool even_in);
 
+// Plane sums (statistics) and plane means <uv>, <wv> of the two wall planes of
+// members [e0, e0 + ec), computed spectrally from the stage fields.
+hipError_t launch_wall_sums(int precision, const void* vel, double* psum, double* means, int My, int E, int K,
+                            int NZ, int P, double kxs, double kzs, int e0, int ec, hipStream_t s);
+
 // Shared-mean ensembles: member averages of the n_x = 0 column (modes k < NZ)
 // of the advection terms and plane means (in place, every member), and of the
 // n_x = 0 column of two state-shaped buffers plus, if U is non-null, the mean

@@ -184,7 +184,80 @@ __global__ void share_columns(double* __restrict__ v, double* __restrict__ eta, 
   }
 }
 
+// Plane sums of the two wall planes from the spectral stage fields (Parseval
+// over the stored half spectrum, weight 1 for n_x = 0 and 2 otherwise), so
+// that the advection kernel never has to visit them: <u^2>, <v^2>, <w^2>,
+// <|grad u|^2> (with dv/dy = -(du/dx + dw/dz)) and the means <uv>, <wv>.  At a
+// no-slip wall only U00 and the wall shears du/dy, dw/dy contribute; the
+// general expressions are evaluated anyway.  One workgroup per (member, wall),
+// fixed-order reduction.
+template <typename VT>
+__global__ void __launch_bounds__(256) wall_sums(const VT* __restrict__ vel, double* __restrict__ psum,
+                                                 double* __restrict__ means, int My, int E, int K, int NZ,
+                                                 int P, double kxs, double kzs, int e0) {
+  const int e = e0 + int(blockIdx.x >> 1);
+  const int j = (blockIdx.x & 1) ? My - 1 : 0;
+  const size_t FS = 2 * size_t(My) * E * K;  // field stride (VT units)
+  const VT* row = vel + 2 * ((size_t(j) * E + e) * K);
+  double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // uu vv ww grad uv wv
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const int nx = k / NZ, iz = k - nx * NZ;
+    const int nz = iz < P ? iz : iz - NZ;
+    const double m = nx == 0 ? 1.0 : 2.0;
+    const double kx = kxs * nx, kz = kzs * nz, k2 = kx * kx + kz * kz;
+    double f[5][2];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      f[c][0] = double(row[c * FS + 2 * k]);
+      f[c][1] = double(row[c * FS + 2 * k + 1]);
+    }
+    const double uu = f[0][0] * f[0][0] + f[0][1] * f[0][1];
+    const double vv = f[1][0] * f[1][0] + f[1][1] * f[1][1];
+    const double ww = f[2][0] * f[2][0] + f[2][1] * f[2][1];
+    const double uy = f[3][0] * f[3][0] + f[3][1] * f[3][1];
+    const double wy = f[4][0] * f[4][0] + f[4][1] * f[4][1];
+    const double vr = kx * f[0][0] + kz * f[2][0], vi = kx * f[0][1] + kz * f[2][1];  // |dv/dy|
+    q[0] += m * uu;
+    q[1] += m * vv;
+    q[2] += m * ww;
+    q[3] += m * (k2 * (uu + vv + ww) + uy + wy + vr * vr + vi * vi);
+    q[4] += m * (f[0][0] * f[1][0] + f[0][1] * f[1][1]);
+    q[5] += m * (f[2][0] * f[1][0] + f[2][1] * f[1][1]);
+  }
+  __shared__ double red[6][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double x = q[c];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[c][wv] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[6];
+    for (int c = 0; c < 6; ++c) t[c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+    const size_t je = size_t(j) * E + e, ME = size_t(My) * E;
+    psum[size_t(PS_UU) * ME + je] = t[0];
+    psum[size_t(PS_VV) * ME + je] = t[1];
+    psum[size_t(PS_WW) * ME + je] = t[2];
+    psum[size_t(PS_GRAD) * ME + je] = t[3];
+    means[je] = t[4];
+    means[ME + je] = t[5];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_wall_sums(int precision, const void* vel, double* psum, double* means, int My, int E, int K,
+                            int NZ, int P, double kxs, double kzs, int e0, int ec, hipStream_t s) {
+  if (precision == 0)
+    hipLaunchKernelGGL(wall_sums<double>, dim3(2 * ec), dim3(256), 0, s, static_cast<const double*>(vel), psum,
+                       means, My, E, K, NZ, P, kxs, kzs, e0);
+  else
+    hipLaunchKernelGGL(wall_sums<float>, dim3(2 * ec), dim3(256), 0, s, static_cast<const float*>(vel), psum,
+                       means, My, E, K, NZ, P, kxs, kzs, e0);
+  return hipGetLastError();
+}
 
 hipError_t launch_member_mean(int precision, void* nl, double* means, int My, int E, int K, int NZ,
                               hipStream_t s) {
@@ -235,7 +308,9 @@ hipError_t launch_profile_from_device(const double* src, double* dst, int E0, in
 
 // Resolve the statistics and layout kernels on the current device.
 hipError_t misc_preload() {
-  const void* fns[8] = {reinterpret_cast<const void*>(&stats_kernel),
+  const void* fns[10] = {reinterpret_cast<const void*>(&stats_kernel),
+                        reinterpret_cast<const void*>(&wall_sums<double>),
+                        reinterpret_cast<const void*>(&wall_sums<float>),
                         reinterpret_cast<const void*>(&state_to_device),
                         reinterpret_cast<const void*>(&state_from_device),
                         reinterpret_cast<const void*>(&profile_to_device),
