@@ -35,13 +35,7 @@ def single(g):
                         g["members"], g["dt"])
 
 
-GRAPH_SKIP = pytest.mark.skip(reason=(
-    "the process segfaulted (host side) in dns_step when this graph-mode case was the first GPU work "
-    "of a fresh process (nested stream forks under capture); it passed when other tests ran first. "
-    "Its cause is not shown yet, so the case stays off the GPU"))
-
-
-@pytest.mark.parametrize("graph", [pytest.param(1, marks=GRAPH_SKIP), 0])
+@pytest.mark.parametrize("graph", [1, 0])
 @pytest.mark.parametrize("precision", [dns.PREC_FP64, dns.PREC_MIXED_FP32])
 def test_grouped_equals_groups_run_alone_bitwise(graph, precision):
     say(f"case: grouped 3 groups, 10 steps, graph={graph} precision={precision} vs alone")
