@@ -29,7 +29,36 @@ def say(*a):
     sys.stdout.flush()
 
 
-def run(name, precision, seed=None):
+def member_profiles(w, ops, v, eta, U):
+    """Per-member U(y), u'^2(y) and wall shear from a state snapshot (host
+    post-processing: u from v and eta per mode, Parseval over the half spectrum)."""
+    L, P, NZ = w["Nx"] // 2, w["Nz"] // 2, w["Nz"] - 1
+    nx = np.arange(L)[:, None]
+    iz = np.arange(NZ)[None, :]
+    nz = np.where(iz < P, iz, iz - NZ)
+    kx = 2 * np.pi * nx / w["Lx"] * np.ones_like(nz)
+    kz = 2 * np.pi * nz / w["Lz"] * np.ones_like(nx)
+    k2 = np.where(kx ** 2 + kz ** 2 > 0, kx ** 2 + kz ** 2, 1.0)
+    mk = np.where(nx == 0, 1.0, 2.0) * np.ones_like(kz)
+    mk[0, 0] = 0.0                                   # fluctuations only
+    dv = np.einsum("jn,elmn->elmj", ops["D1c"], v)   # all nodes
+    etaf = np.zeros_like(dv)
+    etaf[..., 1:-1] = eta
+    u = (1j * kx[None, :, :, None] * dv - 1j * kz[None, :, :, None] * etaf) / k2[None, :, :, None]
+    uu = np.einsum("lm,elmj->ej", mk, np.abs(u) ** 2)
+    tau = 0.5 * (np.abs(U @ ops["D1"][0]) + np.abs(U @ ops["D1"][-1])) / w["Re"]
+    return U, uu, tau
+
+
+def bootstrap_se(samples, rng, nboot=400):
+    """Relative standard error of the member mean (2-norm over y for profiles)."""
+    E = samples.shape[0]
+    mean = samples.mean(axis=0)
+    boots = np.array([samples[rng.integers(0, E, E)].mean(axis=0) for _ in range(nboot)])
+    return float(np.linalg.norm(boots.std(axis=0)) / np.linalg.norm(mean))
+
+
+def run(name, precision, seed=None, sample_every=0):
     w = inputs.WORKLOADS[name]
     ens = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"],
                        w["ensemble"], w["dt"])
@@ -41,9 +70,26 @@ def run(name, precision, seed=None):
     ens.step(half)
     ens.set_option(dns.OPT_STATS, 1)
     ens.stats_reset()
-    ens.step(w["steps"] - half)
+    per = None
+    if sample_every:
+        ops = dns.host_operators(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], w["dt"], 1)
+        acc = None
+        done = 0
+        while done < w["steps"] - half:
+            n = min(sample_every, w["steps"] - half - done)
+            ens.step(n)
+            done += n
+            v, eta, U, W = ens.get_state()
+            snap = member_profiles(w, ops, v, eta, U)
+            acc = [a for a in snap] if acc is None else [a + b for a, b in zip(acc, snap)]
+            nsamp = 1 if per is None else per + 1
+            per = nsamp
+        per = [a / per for a in acc]
+    else:
+        ens.step(w["steps"] - half)
     s = ens.stats()
     s["seconds"] = time.perf_counter() - t0
+    s["members"] = per
     ens.close()
     return s
 
@@ -61,7 +107,7 @@ def compare(a, b):
 @pytest.mark.parametrize("name", ["couette-re600-32x49x32-e64", "channel-re4200-64x97x64-e16"])
 def test_mixed_statistics_match_fp64(name):
     say(f"case: statistics {name}: FP64, mixed, split-BF16, FP64 with another seed")
-    ref = run(name, dns.PREC_FP64)
+    ref = run(name, dns.PREC_FP64, sample_every=50)
     mix = run(name, dns.PREC_MIXED_FP32)
     spl = run(name, dns.PREC_MIXED_3XBF16)
     other = run(name, dns.PREC_FP64, seed=inputs.WORKLOADS[name]["seed"] + 100)
@@ -74,6 +120,13 @@ def test_mixed_statistics_match_fp64(name):
            "seconds_fp64": ref["seconds"], "seconds_mixed": mix["seconds"],
            "seconds_split": spl["seconds"],
            "failed": int(ref["failed"].sum() + mix["failed"].sum() + spl["failed"].sum())}
+    # the FP64 run's own sampling error: bootstrap over members of member-averaged
+    # profiles sampled every 50 steps (host post-processing of state snapshots)
+    rng = np.random.default_rng(0)
+    U_m, uu_m, tau_m = ref["members"]
+    rec["fp64_bootstrap_se"] = {"U": bootstrap_se(U_m, rng), "urms": bootstrap_se(np.sqrt(uu_m), rng),
+                                "tau_w": bootstrap_se(tau_m[:, None], rng)}
+    rec["underpowered"] = bool(max(rec["fp64_bootstrap_se"].values()) > 0.005)
     say(json.dumps(rec))
     os.makedirs(OUT, exist_ok=True)
     with open(os.path.join(OUT, f"stats_{name}.json"), "w") as f:
