@@ -11,7 +11,7 @@ in the HIP library; torch only holds device memory):
                  in a seeded random order, with a cosine learning-rate decay;
   * spin_up() -- apply the network ``applications`` times to members' channel
                  form and rebuild admissible states from the prediction; the
-                 DNS then continues and judges every member.
+                 DNS then continues and checks every member.
 """
 
 import argparse
@@ -85,15 +85,15 @@ def train(net, data, epochs, batch, lr=2e-3, lr_final=1e-4, weight_decay=1e-4, s
     return history
 
 
-def spin_up(ens, net, applications, member0=0, count=None, judge=0):
+def spin_up(ens, net, applications, member0=0, count=None, check_steps=0):
     """Advance members [member0, member0 + count) by ``applications`` network
     steps and hand the admissible states back to the DNS.
 
-    judge > 0: the DNS then runs ``judge`` steps; members it flags non-finite
+    check_steps > 0: the DNS then runs ``check_steps`` steps; members it flags non-finite
     get their original state back and re-run those steps as plain DNS
     members.  Returns the number of members the DNS rejected."""
     count = ens.E - member0 if count is None else count
-    original = ens.get_state(member0, count) if judge else None
+    original = ens.get_state(member0, count) if check_steps else None
     C, P = channel_shape(ens)
     x = torch.empty((count, C, P), dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
@@ -106,10 +106,10 @@ def spin_up(ens, net, applications, member0=0, count=None, judge=0):
         x, y = y, x
     net.sync()
     ens.set_channels(x, member0)
-    if not judge:
+    if not check_steps:
         return 0
     before = ens.get_state()
-    ens.step(judge)
+    ens.step(check_steps)
     failed = ens.stats(allow_nonfinite=True)["failed"][member0:member0 + count].astype(bool)
     if not failed.any():
         return 0
@@ -120,7 +120,7 @@ def spin_up(ens, net, applications, member0=0, count=None, judge=0):
         m = member0 + i
         v[m], eta[m], U[m], W[m] = (o[i] for o in original)
     ens.set_state(v, eta, U, W)
-    ens.step(judge)
+    ens.step(check_steps)
     return int(failed.sum())
 
 
@@ -143,7 +143,7 @@ def profile_distance(a, b):
                           for k in ("U", "urms", "vrms", "wrms")]))
 
 
-def gain(make, net, held, applications, gap, win, windows, judge=0):
+def gain(make, net, held, applications, gap, win, windows, check_steps=0):
     """Spun-up vs DNS-only ensembles of the same held-out initial states.
 
     Returns the per-window distances of the spun-up ensemble (after the
@@ -156,7 +156,7 @@ def gain(make, net, held, applications, gap, win, windows, judge=0):
     ref.close()
     arm = make(held[0].shape[0])
     arm.set_state(*held)
-    rejected = spin_up(arm, net, applications, judge=judge)
+    rejected = spin_up(arm, net, applications, check_steps=check_steps)
     S = profile_windows(arm, windows, win)
     arm.close()
     d_s = [profile_distance(S[h], R[h + skip]) for h in range(windows)]
@@ -207,7 +207,7 @@ def main():
     del blocks
     torch.cuda.empty_cache()
     held = inputs.workload_state(name, ensemble=args.held_out, seed=3001)
-    d_s, d_0, S, rejected = gain(make, net, held, args.applications, args.gap, 100, 8, judge=50)
+    d_s, d_0, S, rejected = gain(make, net, held, args.applications, args.gap, 100, 8, check_steps=50)
     out = {"pairs": npairs, "rounds": rounds, "dns_steps_for_data": rounds * (args.snapshots - 1) * args.gap,
            "data_seconds": t_data, "persistence_loss": persistence, "epoch_loss": hist,
            "train_seconds": t_train, "train_steps": steps, "train_samples_per_s": steps * args.batch / t_train,
