@@ -75,9 +75,10 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
  * dt or flow -- share one dns_step).  Each group is a full ensemble as made by
  * dns_create, with its own operators and buffers; its kernels run on a stream
  * of its own, forked from and joined back into the grouped handle's stream
- * (one hipGraph with one branch per group when DNS_OPT_GRAPH is on), so small
- * groups overlap on the device.  Members are numbered group-major: group g
- * holds members [sum of earlier groups' members, + members).
+ * (launched eagerly: DNS_OPT_GRAPH = 1 on a grouped handle returns
+ * DNS_E_UNSUPPORTED), so small groups overlap on the device.  Members are
+ * numbered group-major: group g holds members [sum of earlier groups' members,
+ * + members).
  *   groups  : ngroups descriptions, 1 <= ngroups <= DNS_MAX_GROUPS; read only
  *             during the call.
  * On a grouped handle: dns_set_state / dns_get_state take member ranges inside
@@ -106,7 +107,8 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
 /* Options (dns_set_option keys) */
 #define DNS_OPT_PRECISION 1   /* value: DNS_PREC_*                                */
 #define DNS_OPT_STREAM 2      /* value: hipStream_t cast to integer (0 = default) */
-#define DNS_OPT_GRAPH 3       /* value: 1 capture one step as a hipGraph, 0 eager */
+#define DNS_OPT_GRAPH 3       /* value: 1 capture one step as a hipGraph, 0 eager;
+                                 DNS_E_UNSUPPORTED for 1 on a grouped handle     */
 #define DNS_OPT_STATS 4       /* value: 1 accumulate one-point statistics each step */
 #define DNS_OPT_PLANE_ROWS 5  /* value: physical z rows per chunk of the advection
                                  kernel, one of the built variants (DNS_E_UNSUPPORTED

@@ -35,7 +35,12 @@ def single(g):
                         g["members"], g["dt"])
 
 
-@pytest.mark.parametrize("graph", [1, 0])
+GRAPH_SKIP = pytest.mark.skip(
+    reason="graph capture of a grouped step is disabled (DNS_E_UNSUPPORTED): capturing it crashed the "
+           "host process inside dns_step intermittently, with no cause shown in the library")
+
+
+@pytest.mark.parametrize("graph", [pytest.param(1, marks=GRAPH_SKIP), 0])
 @pytest.mark.parametrize("precision", [dns.PREC_FP64, dns.PREC_MIXED_FP32])
 def test_grouped_equals_groups_run_alone_bitwise(graph, precision):
     say(f"case: grouped 3 groups, 10 steps, graph={graph} precision={precision} vs alone")
@@ -102,6 +107,11 @@ def test_grouped_routing_and_group_handles():
     st0 = inputs.group_state(g0, members=2)
     with pytest.raises(dns.DnsError):
         grp.set_state(*st0, member0=g0["members"] - 1)
+    # a grouped step is not captured as a graph; the handle stays usable
+    with pytest.raises(dns.DnsError) as err:
+        grp.set_option(dns.OPT_GRAPH, 1)
+    assert err.value.code == dns.DNS_E_UNSUPPORTED
+    grp.set_option(dns.OPT_GRAPH, 0)
     # profiles are per group: the group's handle gives them
     grp.set_option(dns.OPT_STATS, 1)
     grp.step(3)
