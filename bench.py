@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Vector ALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.  Packed
-# FP32 is disabled in this build, so FP32 and FP64 vector peaks are equal.
+# FP32 instructions are disabled at compile time, so FP32 and FP64 vector peaks are equal.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 

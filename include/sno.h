@@ -6,7 +6,7 @@
  * accumulating statistics).  Here a small spectral neural operator (SNO), trained
  * on pairs of states that the DNS itself produces some steps apart, advances new
  * members through most of that transient; the plain DNS then continues from an
- * admissible state rebuilt from the prediction and judges every member.
+ * admissible state rebuilt from the prediction and checks every member.
  *
  * Channel form of a member's state: u, v, w on the 3/2-padded x-z grid
  * (Mx = 3Nx/2 by Mz = 3Nz/2 points, the grid of the advection term, Sec. 3.2)

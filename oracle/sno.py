@@ -5,7 +5,7 @@ for clarity.  The paper starts every ensemble member from a perturbed state and
 lets the DNS run through the transient to turbulence; the learned spin-up
 replaces most of that transient by a few applications of a small spectral
 neural operator (a Fourier neural operator acting on x-z planes), after which
-the plain DNS continues and judges every member.
+the plain DNS continues and checks every member.
 
 Channel form of a state (one member):
   * u, v, w on the 3/2-padded x-z grid (Mx x Mz points, as used for the
