@@ -146,9 +146,18 @@ __device__ __forceinline__ void dcontract(const ModeArgs& a, int which, const do
 }
 
 template <typename VT>
+struct Pair;
+template <> struct Pair<float> { typedef float2 type; };
+template <> struct Pair<double> { typedef double2 type; };
+
+// One complex value as one vector store (p is even in VT units, so aligned to
+// the pair): the real and imaginary parts never reach memory separately.
+template <typename VT>
 __device__ __forceinline__ void st_c(VT* p, double re, double im) {
-  p[0] = VT(re);
-  p[1] = VT(im);
+  typename Pair<VT>::type v;
+  v.x = VT(re);
+  v.y = VT(im);
+  *reinterpret_cast<typename Pair<VT>::type*>(p) = v;
 }
 
 }  // namespace
@@ -217,15 +226,19 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   const int KSe = (2 * He + 3) / 4, KSo = (2 * Ho + 3) / 4;
 
   // write the FH pair k of buffer B (re/im columns 2c, 2c+1) to stage field f
+  // (node k takes even + odd, node My-1-k even - odd).  Both stores are
+  // unconditional so that each stays one vector store: at the centre node of
+  // an odd grid (k = Fo, no odd part) both address node k, and the second,
+  // in program order, leaves er - 0 = er exactly.
   auto write_pair = [&](const double* B, int k, int c, int f) {
     const double er = B[k * CRP + 2 * c], ei = B[k * CRP + 2 * c + 1];
+    double orr = 0.0, oi = 0.0;
     if (k < Fo) {
-      const double orr = B[(Fe + k) * CRP + 2 * c], oi = B[(Fe + k) * CRP + 2 * c + 1];
-      st_c(vel + f * FS + sb(k, c), er + orr, ei + oi);
-      st_c(vel + f * FS + sb(My - 1 - k, c), er - orr, ei - oi);
-    } else {
-      st_c(vel + f * FS + sb(k, c), er, ei);
+      orr = B[(Fe + k) * CRP + 2 * c];
+      oi = B[(Fe + k) * CRP + 2 * c + 1];
     }
+    st_c(vel + f * FS + sb(k, c), er + orr, ei + oi);
+    st_c(vel + f * FS + sb(My - 1 - k, c), er - orr, ei - oi);
   };
 
   if (!mean_group) {
