@@ -207,11 +207,27 @@ typedef struct {
   int on_device;
 } dns_state_view;
 
-/* Load members [member0, member0+count) from s.  Wall values of U00/W00 must
- * match the boundary conditions (Couette U00(-1) = -Uw, U00(1) = Uw; channel
- * 0; W00 = 0) within 1e-12.  Clears the members' failure flags.
- * Errors: DNS_E_INVALID. */
+/* Load members [member0, member0+count) from s.  Every member must satisfy the
+ * rules of dns_check_state (checked on the host; device views have their
+ * profiles and n_x = 0 columns copied back for it); the state is left as it
+ * was when a member does not.  Clears the members' failure flags.
+ * Errors: DNS_E_INVALID (the message names the member and the rule). */
 int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s);
+
+/* Host-side check of `count` members of a host state view (on_device = 0)
+ * against what dns_set_state requires for an ensemble of flow g->flow, wall
+ * speed g->Uw and grid Nx x Ny x Nz; needs no handle and no GPU.
+ *   - U00/W00 wall values match the boundary conditions (Sec. 2: Couette
+ *     U00(-1) = -Uw, U00(1) = Uw; channel 0; W00 = 0) within 1e-12;
+ *   - the (0,0) mode of v_hat and of eta_hat is zero, and their n_x = 0
+ *     column is Hermitian, f(0,-n_z) = conj f(0,n_z) (Appendix A: only half
+ *     of the conjugate pairs is stored), both within 1e-12 of the largest
+ *     |f| of that member's column.
+ * NaN or Inf in a wall value or in the n_x = 0 column fails the check (other
+ * entries may hold anything: a non-finite member is accepted and flagged by
+ * the step).  Returns DNS_OK, or DNS_E_INVALID with a message naming the
+ * member and the rule (dns_last_error(NULL)). */
+int dns_check_state(const dns_geometry* g, int Nx, int Ny, int Nz, int count, const dns_state_view* s);
 
 /* Additive forcing of the (Lap v, eta) equations of members [member0,
  * member0+count): d(Lap v)/dt and d(eta)/dt gain f_lapv and f_eta, held
@@ -267,6 +283,18 @@ int dns_step(dns_handle* h, int nsteps);
  *   profiles    averaged over members and the samples since the last reset;
  *   tau_w       Couette mean |U'| at the walls / Re, channel (U'(-1)-U'(1))/(2Re)
  *   re_tau      Re sqrt(tau_w)
+ *   member_profiles  [member][8][Ny]: each member's time averages since the
+ *               last reset of U00, W00, U00^2, W00^2 and of the x-z plane
+ *               means of u^2, v^2, w^2 and u v (mean flow included: the plane
+ *               mean of u^2 is U00^2 + sum over k != 0 of m_k |u_k|^2, m_k = 1
+ *               for n_x = 0, else 2), in that order.  The pooled statistics
+ *               above are, per node, U = <U00>, u'^2 = <u^2> - U^2,
+ *               v'^2 = <v^2>, w'^2 = <w^2> - W^2, u'v' = <u v> with <.> the
+ *               mean over members of these arrays, so resampling members (a
+ *               bootstrap) needs only them.  Zero before the first sample.
+ *               Must be NULL on grouped handles.
+ *   member_tau  [member][2]: each member's time averages of U'(-1)/Re and
+ *               U'(+1)/Re since the last reset (group-major on grouped handles)
  * Synchronises.  Returns DNS_E_NONFINITE if any member failed, else DNS_OK. */
 typedef struct {
   double* energy;
@@ -288,6 +316,8 @@ typedef struct {
   double re_tau;
   long long samples;
   long long steps;
+  double* member_profiles;
+  double* member_tau;
 } dns_stats_out;
 int dns_stats(dns_handle* h, dns_stats_out* o);
 

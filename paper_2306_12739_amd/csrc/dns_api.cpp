@@ -520,9 +520,72 @@ int check_dims(int Nx, int Ny, int Nz, int E) {
   return DNS_OK;
 }
 
+// Requirements of a state on its n_x = 0 column (Appendix A stores half of
+// the conjugate pairs: f(0, -n_z) = conj f(0, n_z); the (0,0) mode of v and
+// eta is zero, the mean flow living in U00, W00).  col: one member's column,
+// NZ x N interleaved complex values with n_z in FFT order.  Both rules hold
+// within 1e-12 of the column's largest entry; a NaN fails every comparison.
+const char* column_violation(const double* col, int NZ, int N) {
+  const int P = (NZ + 1) / 2;
+  double top = 0.0;
+  for (size_t q = 0; q < size_t(NZ) * N * 2; ++q) top = std::fmax(top, std::fabs(col[q]));
+  const double tol = 1e-12 * top;
+  for (int j = 0; j < N; ++j)
+    if (!(std::hypot(col[2 * j], col[2 * j + 1]) <= tol)) return "the (0,0) mode is not zero";
+  for (int iz = 1; iz < NZ; ++iz) {
+    const int nz = iz < P ? iz : iz - NZ;
+    const int mirror = (NZ - nz) % NZ;
+    for (int j = 0; j < N; ++j) {
+      const double* a = col + 2 * (size_t(iz) * N + j);
+      const double* b = col + 2 * (size_t(mirror) * N + j);
+      if (!(std::hypot(a[0] - b[0], a[1] + b[1]) <= tol)) return "the n_x = 0 column is not Hermitian";
+    }
+  }
+  return nullptr;
+}
+
+// Wall values of one member's U00, W00 (My nodes) against the boundary
+// conditions (Eq. (b_ve) and the wall speeds of Sec. 2); NaN fails.
+const char* wall_violation(const double* U, const double* W, int My, double Ubot, double Utop) {
+  if (!(std::fabs(U[0] - Ubot) <= 1e-12) || !(std::fabs(U[My - 1] - Utop) <= 1e-12) ||
+      !(std::fabs(W[0]) <= 1e-12) || !(std::fabs(W[My - 1]) <= 1e-12))
+    return "U00/W00 wall values do not match the boundary conditions";
+  return nullptr;
+}
+
+// Host state view (host layout of dns_state_view) of count members.
+int check_host_state(dns_handle* h, int L, int NZ, int N, int My, double Ubot, double Utop, int count,
+                     const dns_state_view* s) {
+  const size_t per = size_t(L) * NZ * N * 2;
+  for (int m = 0; m < count; ++m) {
+    std::string why;
+    if (const char* w = wall_violation(s->U00 + size_t(m) * My, s->W00 + size_t(m) * My, My, Ubot, Utop))
+      why = w;
+    else if (const char* c = column_violation(s->v_hat + m * per, NZ, N))
+      why = std::string("v_hat: ") + c;
+    else if (const char* c2 = column_violation(s->eta_hat + m * per, NZ, N))
+      why = std::string("eta_hat: ") + c2;
+    if (!why.empty()) return fail(h, DNS_E_INVALID, "member " + std::to_string(m) + ": " + why);
+  }
+  return DNS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int dns_check_state(const dns_geometry* g, int Nx, int Ny, int Nz, int count, const dns_state_view* s) {
+  if (!g || !s || !s->v_hat || !s->eta_hat || !s->U00 || !s->W00)
+    return fail(nullptr, DNS_E_INVALID, "geometry or state view is NULL");
+  if (s->on_device) return fail(nullptr, DNS_E_INVALID, "dns_check_state reads host views only");
+  if (g->flow != DNS_FLOW_COUETTE && g->flow != DNS_FLOW_POISEUILLE)
+    return fail(nullptr, DNS_E_INVALID, "unknown flow type");
+  if (Nx <= 0 || Nz <= 0 || (Nx % 2) || (Nz % 2) || Ny < 5 || count < 1)
+    return fail(nullptr, DNS_E_INVALID, "need even Nx, Nz > 0, Ny >= 5 and count >= 1");
+  const double Uw = g->Uw > 0 ? g->Uw : 1.0;
+  const double Ubot = g->flow == DNS_FLOW_COUETTE ? -Uw : 0.0, Utop = g->flow == DNS_FLOW_COUETTE ? Uw : 0.0;
+  return check_host_state(nullptr, Nx / 2, Nz - 1, Ny - 2, Ny, Ubot, Utop, count, s);
+}
 
 int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ensemble, double dt,
                dns_handle** out) {
@@ -942,21 +1005,26 @@ int dns_set_state(dns_handle* h, int member0, int count, const dns_state_view* s
     return fail(h, DNS_E_INVALID, "member range out of bounds");
   const size_t nspec = size_t(count) * h->K * h->N * 2;
   const size_t nprof = size_t(count) * h->My;
-  // validate on the host (copy device views back first)
-  std::vector<double> U(nprof), W(nprof), v0;
+  // validate on the host: profiles and the n_x = 0 columns (copied back from
+  // device views first; the other modes carry no requirement)
+  std::vector<double> U(nprof), W(nprof);
   if (s->on_device) {
+    const size_t col = size_t(h->NZ) * h->N * 2, per = size_t(h->K) * h->N * 2;
+    std::vector<double> vc(count * col), ec(count * col);
     HIP_OR_FAIL(h, hipMemcpy(U.data(), s->U00, nprof * sizeof(double), hipMemcpyDeviceToHost));
     HIP_OR_FAIL(h, hipMemcpy(W.data(), s->W00, nprof * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(h, hipMemcpy2D(vc.data(), col * sizeof(double), s->v_hat, per * sizeof(double),
+                               col * sizeof(double), count, hipMemcpyDeviceToHost));
+    HIP_OR_FAIL(h, hipMemcpy2D(ec.data(), col * sizeof(double), s->eta_hat, per * sizeof(double),
+                               col * sizeof(double), count, hipMemcpyDeviceToHost));
+    const dns_state_view hv{vc.data(), ec.data(), U.data(), W.data(), 0};
+    const int rc = check_host_state(h, 1, h->NZ, h->N, h->My, h->Ubot, h->Utop, count, &hv);
+    if (rc) return rc;
   } else {
     std::memcpy(U.data(), s->U00, nprof * sizeof(double));
     std::memcpy(W.data(), s->W00, nprof * sizeof(double));
-  }
-  for (int m = 0; m < count; ++m) {
-    const double ub = U[size_t(m) * h->My], ut = U[size_t(m) * h->My + h->My - 1];
-    const double wb = W[size_t(m) * h->My], wt = W[size_t(m) * h->My + h->My - 1];
-    if (std::fabs(ub - h->Ubot) > 1e-12 || std::fabs(ut - h->Utop) > 1e-12 || std::fabs(wb) > 1e-12 ||
-        std::fabs(wt) > 1e-12)
-      return fail(h, DNS_E_INVALID, "U00/W00 wall values do not match the boundary conditions");
+    const int rc = check_host_state(h, h->L, h->NZ, h->N, h->My, h->Ubot, h->Utop, count, s);
+    if (rc) return rc;
   }
   int rc = ensure_staging(h, 2 * nspec * sizeof(double));
   if (rc) return rc;
@@ -1281,7 +1349,7 @@ int dns_stats(dns_handle* h, dns_stats_out* o) {
   ORDER_AFTER_PARENT(h);
   if (!o) return fail(h, DNS_E_INVALID, "output is NULL");
   if (h->grouped()) {
-    if (o->U || o->W || o->urms || o->vrms || o->wrms || o->uv)
+    if (o->U || o->W || o->urms || o->vrms || o->wrms || o->uv || o->member_profiles)
       return fail(h, DNS_E_INVALID,
                   "profiles of a grouped handle differ per group: read them from dns_group_handle");
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
@@ -1299,6 +1367,7 @@ int dns_stats(dns_handle* h, dns_stats_out* o) {
       so.tau_lower = at(o->tau_lower);
       so.tau_upper = at(o->tau_upper);
       so.failed = o->failed ? o->failed + b : nullptr;
+      so.member_tau = o->member_tau ? o->member_tau + 2 * size_t(b) : nullptr;
       const int rc = dns_stats(h->sub[g], &so);
       if (rc == DNS_E_NONFINITE) out = rc;
       else if (rc) return forward(h, h->sub[g], rc);
@@ -1344,6 +1413,17 @@ int dns_stats(dns_handle* h, dns_stats_out* o) {
   }
   o->samples = h->samples;
   o->steps = h->steps;
+  // per-member time averages (zero before the first sample)
+  const double inv_t = h->samples > 0 ? 1.0 / double(h->samples) : 0.0;
+  if (o->member_profiles)
+    for (int e = 0; e < E; ++e)
+      for (int q = 0; q < NPA; ++q)
+        for (int j = 0; j < My; ++j)
+          o->member_profiles[(size_t(e) * NPA + q) * My + j] = acc[(size_t(q) * My + j) * E + e] * inv_t;
+  if (o->member_tau)
+    for (int e = 0; e < E; ++e)
+      for (int side = 0; side < 2; ++side)
+        o->member_tau[2 * size_t(e) + side] = acc[size_t(NPA) * My * E + size_t(side) * E + e] * inv_t / h->Re;
   if (h->samples > 0) {
     const double inv = 1.0 / (double(h->samples) * E);
     for (int j = 0; j < My; ++j) {

@@ -54,7 +54,7 @@ EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "d
             "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
             "dns_create_grouped", "dns_group_handle", "dns_tune",
             "dns_get_channels", "dns_set_channels", "dns_set_forcing",
-            "dns_perturbation_energy", "dns_orthonormalize",
+            "dns_perturbation_energy", "dns_orthonormalize", "dns_check_state",
             "sno_create", "sno_set_option", "sno_num_params", "sno_set_params", "sno_get_params",
             "sno_forward", "sno_loss_grad", "sno_train_step", "sno_sync", "sno_last_error",
             "sno_destroy"]
@@ -115,7 +115,7 @@ class StatsOut(ctypes.Structure):
                 ("failed", _IP), ("U", _DP), ("W", _DP), ("urms", _DP), ("vrms", _DP),
                 ("wrms", _DP), ("uv", _DP), ("tau_w", ctypes.c_double),
                 ("re_tau", ctypes.c_double), ("samples", ctypes.c_longlong),
-                ("steps", ctypes.c_longlong)]
+                ("steps", ctypes.c_longlong), ("member_profiles", _DP), ("member_tau", _DP)]
 
 
 _lib = None
@@ -135,6 +135,8 @@ def library(path=LIB_PATH):
     lib.dns_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
     lib.dns_set_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(StateView)]
     lib.dns_get_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(StateView)]
+    lib.dns_check_state.argtypes = [ctypes.POINTER(Geometry), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(StateView)]
     lib.dns_step.argtypes = [vp, ctypes.c_int]
     lib.dns_stats.argtypes = [vp, ctypes.POINTER(StatsOut)]
     lib.dns_stats_reset.argtypes = [vp]
@@ -177,6 +179,21 @@ def library(path=LIB_PATH):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def check_state(flow, Nx, Ny, Nz, v, eta, U, W, Uw=1.0):
+    """dns_check_state on host arrays (no GPU needed); raises DnsError with
+    the library's message when a member breaks a rule of dns_set_state."""
+    lib = library()
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    eta = np.ascontiguousarray(eta, dtype=np.complex128)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    sv = StateView(v.ctypes.data, eta.ctypes.data, U.ctypes.data, W.ctypes.data, 0)
+    g = Geometry(flow, 1.0, 1.0, Uw, 0.0)
+    rc = lib.dns_check_state(ctypes.byref(g), Nx, Ny, Nz, v.shape[0], ctypes.byref(sv))
+    if rc != DNS_OK:
+        raise DnsError(rc, lib.dns_last_error(None).decode())
 
 
 def host_operators(flow, Re, Lx, Lz, Nx, Ny, Nz, dt, h_index, Uw=1.0, v_discretization=0):
@@ -325,13 +342,21 @@ class Ensemble:
     def stats_reset(self):
         return self._check(self.lib.dns_stats_reset(self.h))
 
+    # member_profiles rows: U00, W00, U00^2, W00^2 and the plane means of u^2,
+    # v^2, w^2, u v (mean flow included), each a time average per member
+    MEMBER_PROFILES = ("U", "W", "U2", "W2", "uu", "vv", "ww", "uv")
+
     def stats(self, allow_nonfinite=False):
+        """Diagnostics and statistics (dns_stats).  'member_profiles' is
+        (E, 8, Ny) in the order of MEMBER_PROFILES, 'member_tau' (E, 2)."""
         E, My = self.E, self.Ny
         out = {k: np.zeros(E) for k in ("energy", "dissipation", "power", "flux", "gamma",
                                          "div_max", "tau_lower", "tau_upper")}
         out["failed"] = np.zeros(E, dtype=np.int32)
         for k in ("U", "W", "urms", "vrms", "wrms", "uv"):
             out[k] = np.zeros(My)
+        out["member_profiles"] = np.zeros((E, 8, My))
+        out["member_tau"] = np.zeros((E, 2))
         so = StatsOut()
         for k, arr in out.items():
             setattr(so, k, arr.ctypes.data_as(_IP if k == "failed" else _DP))
@@ -495,6 +520,7 @@ class GroupedEnsemble:
         out = {k: np.zeros(E) for k in ("energy", "dissipation", "power", "flux", "gamma",
                                          "div_max", "tau_lower", "tau_upper")}
         out["failed"] = np.zeros(E, dtype=np.int32)
+        out["member_tau"] = np.zeros((E, 2))
         so = StatsOut()
         for k, arr in out.items():
             setattr(so, k, arr.ctypes.data_as(_IP if k == "failed" else _DP))

@@ -114,3 +114,72 @@ def test_binding_constants_match_the_header():
     assert {"OPT_ADVECTION", "ADV_ADVECTIVE", "ADV_ROTATIONAL"} <= set(defs)
     for name, value in defs.items():
         assert getattr(dns, name) == int(value), name
+
+
+# ---- dns_check_state: the host rules of dns_set_state (no GPU) -------------------
+def _states_used_by_the_gpu_paths():
+    from paper_2306_12739_amd import inputs, optimal
+    for name, w in inputs.WORKLOADS.items():
+        if "Nx" in w:
+            yield name, w["flow"], w["Nx"], w["Ny"], w["Nz"], inputs.workload_state(name, ensemble=2)
+    for name, w in inputs.GROUPED_WORKLOADS.items():
+        for g in w["groups"] if isinstance(w, dict) else w:
+            yield name, g["flow"], g["Nx"], g["Ny"], g["Nz"], inputs.group_state(g, members=2)
+    ow = optimal.WORKLOAD
+    base = optimal.base_flow(ow)
+    yield "optimal", ow["flow"], ow["Nx"], ow["Ny"], ow["Nz"], optimal.initial_members(ow, 1, (1, 2), base)
+
+
+def test_check_state_accepts_the_states_the_drivers_load():
+    for name, flow, Nx, Ny, Nz, st in _states_used_by_the_gpu_paths():
+        dns.check_state(flow, Nx, Ny, Nz, *st)
+
+
+def _bad(st, what):
+    v, eta, U, W = (a.copy() for a in st)
+    if what == "v_herm":
+        v[1, 0, 2, 3] += 1e-3                       # (0, 2) no longer conj of (0, -2)
+    elif what == "eta_herm":
+        eta[0, 0, -1, 0] += 1e-3j
+    elif what == "v00":
+        v[0, 0, 0, 4] = 1e-3
+    elif what == "eta00_imag":
+        eta[1, 0, 0, 2] = 1e-3j
+    elif what == "U_wall_nan":
+        U[1, 0] = np.nan
+    elif what == "W_wall":
+        W[0, -1] = 1e-6
+    elif what == "column_nan":
+        v[0, 0, 1, 1] = np.nan
+    return v, eta, U, W
+
+
+@pytest.mark.parametrize("what,rule", [
+    ("v_herm", "v_hat: the n_x = 0 column is not Hermitian"),
+    ("eta_herm", "eta_hat: the n_x = 0 column is not Hermitian"),
+    ("v00", "v_hat: the (0,0) mode is not zero"),
+    ("eta00_imag", "eta_hat: the (0,0) mode is not zero"),
+    ("U_wall_nan", "wall values"),
+    ("W_wall", "wall values"),
+    ("column_nan", "v_hat"),
+])
+def test_check_state_rejects_each_broken_rule(what, rule):
+    from paper_2306_12739_amd import inputs
+    w = inputs.WORKLOADS["couette-re400-16x33x16-e2"]
+    st = inputs.workload_state("couette-re400-16x33x16-e2")
+    dns.check_state(w["flow"], w["Nx"], w["Ny"], w["Nz"], *st)
+    with pytest.raises(dns.DnsError) as ei:
+        dns.check_state(w["flow"], w["Nx"], w["Ny"], w["Nz"], *_bad(st, what))
+    assert ei.value.code == dns.DNS_E_INVALID
+    assert rule in str(ei.value), str(ei.value)
+
+
+def test_check_state_leaves_other_modes_free():
+    """A NaN outside the n_x = 0 column is accepted (the step flags the member)."""
+    from paper_2306_12739_amd import inputs
+    w = inputs.WORKLOADS["couette-re400-16x33x16-e2"]
+    v, eta, U, W = inputs.workload_state("couette-re400-16x33x16-e2")
+    v[1, 1, 2, 5] = np.nan
+    dns.check_state(w["flow"], w["Nx"], w["Ny"], w["Nz"], v, eta, U, W)
+    with pytest.raises(dns.DnsError):     # a channel's walls are at rest
+        dns.check_state(1, w["Nx"], w["Ny"], w["Nz"], v, eta, U, W)

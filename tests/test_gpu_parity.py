@@ -2,8 +2,12 @@
 
 Bars (FP64): stage intermediates within 1e-12 and states within 1e-10 relative
 (2-norm over modes, nodes and members, per field) of the oracle on the same
-seeded inputs.  Sizes span several tiles of every kernel and ragged member
-tiles; the 64x97x64 channel case is checked on sampled members.
+seeded inputs; in the trajectory tests also every (member, n_x, n_z) mode on
+its own scale (parity_metrics.mode_check: error <= 1e-10 of the mode's norm
+plus 1e-13 of the field's largest mode norm) and the n_x = 0 column
+Hermitian to round-off.  Sizes span several tiles of every kernel and ragged
+member tiles; the 64x97x64 channel case is checked on sampled members, and
+the benchmark's exact launch configuration has a test of its own.
 """
 
 import sys
@@ -14,6 +18,7 @@ import pytest
 import oracle
 from oracle import diagnostics as dg
 from paper_2306_12739_amd import dns, inputs
+from parity_metrics import assert_state, mode_check, profile_check, rel, state_report
 
 pytestmark = pytest.mark.gpu
 
@@ -25,9 +30,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 def make_pair(flow, Re, Lx, Lz, Nx, Ny, Nz, E, dt, state):
@@ -38,12 +40,9 @@ def make_pair(flow, Re, Lx, Lz, Nx, Ny, Nz, E, dt, state):
     return gpu, ref
 
 
-def field_errors(gpu, ref, lam):
-    v, eta, U, W = gpu.get_state()
-    return {
-        "v": rel(v, ref.v), "eta": rel(eta, ref.eta),
-        "U-Ulam": rel(U - lam, ref.U - lam), "W": rel(W, ref.W) if np.any(ref.W) else np.abs(W).max(),
-    }
+def field_errors(gpu, ref, lam, bar=1e-10):
+    """Field-wide, per-mode and Hermitian-column errors of the GPU state."""
+    return state_report(gpu.get_state(), (ref.v, ref.eta, ref.U, ref.W), lam, bar)
 
 
 def cfg1_pair(E=2, state=None):
@@ -115,8 +114,7 @@ def test_parity_edge_grids_fp64(case):
     ref.step(steps)
     errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
     say("  errors:", errs)
-    for k, e in errs.items():
-        assert e <= 1e-10, (k, e)
+    assert_state(errs, 1e-10)
     gpu.close()
 
 
@@ -143,8 +141,7 @@ def test_parity_couette_100_steps_fp64():
     ref.step(100)
     errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
     say("errors after 100 steps:", errs)
-    for k, e in errs.items():
-        assert e <= 1e-10, (k, e)
+    assert_state(errs, 1e-10)
     gpu.close()
 
 
@@ -156,54 +153,133 @@ def test_parity_channel_fp64():
     ref.step(20)
     errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
     say("errors:", errs)
-    for k, e in errs.items():
-        assert e <= 1e-10, (k, e)
+    assert_state(errs, 1e-10)
     s = gpu.stats()
     np.testing.assert_allclose(s["flux"], 4.0 / 3.0, rtol=1e-13)
     np.testing.assert_allclose(s["gamma"], ref.gamma, rtol=1e-9)
     gpu.close()
 
 
-def test_parity_couette_32x49x32_ragged_tiles():
-    say("case: couette 32x49x32 E=5 FP64, 5 steps")
+def test_parity_couette_32x49x32_ragged_tiles_100_steps():
+    """Five members: a ragged last member tile (tiles of 4) and chain split."""
+    say("case: couette 32x49x32 E=5 FP64, 100 steps")
     st = inputs.random_state(0, 1.75 * np.pi, 1.2 * np.pi, 32, 49, 32, 5, 0.2, 31, spectrum="k2")
     gpu, ref = make_pair(0, 600.0, 1.75 * np.pi, 1.2 * np.pi, 32, 49, 32, 5, 0.02, st)
-    gpu.step(5)
-    ref.step(5)
-    errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
-    say("errors:", errs)
-    for k, e in errs.items():
-        assert e <= 1e-10, (k, e)
+    lam = ref.laminar_profile()[None, :]
+    for n in (5, 95):
+        gpu.step(n)
+        ref.step(n)
+        errs = field_errors(gpu, ref, lam)
+        say(f"errors after {n} more steps:", errs)
+        assert_state(errs, 1e-10)
     gpu.close()
 
 
-def test_parity_channel_64x97x64_sampled_members():
-    """Full bench size (16 members, launch configuration of the benchmark);
-    the oracle advances members 0 and 15 only (members are independent)."""
-    say("case: channel 64x97x64 E=16 FP64, 1 step, members 0 and 15 vs oracle")
-    name = "channel-re4200-64x97x64-e16"
-    w = inputs.WORKLOADS[name]
-    st = inputs.workload_state(name)
+HEADLINE = "channel-re4200-64x97x64-e16"
+PICK = [0, 15]
+
+
+def headline_sample_oracle(st, steps):
+    """The oracle advanced `steps` FP64 steps on members 0 and 15 of the
+    headline workload (members are independent)."""
+    w = inputs.WORKLOADS[HEADLINE]
+    ref = oracle.OracleDNS(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], len(PICK), w["dt"])
+    ref.set_state(*(a[PICK] for a in st))
+    ref.step(steps)
+    return ref
+
+
+def headline_ensemble(precision, graph, chains, rows=None, tile=None):
+    w = inputs.WORKLOADS[HEADLINE]
     gpu = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], 16, w["dt"])
-    gpu.set_state(*st)
-    pick = [0, 15]
-    sub = tuple(a[pick] for a in st)
-    ref = oracle.OracleDNS(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], 2, w["dt"])
-    ref.set_state(*sub)
-    gpu.step(1)
-    ref.step(1)
+    gpu.set_precision(precision)
+    if rows is not None:
+        gpu.set_option(dns.OPT_PLANE_ROWS, rows)
+    if tile is not None:
+        gpu.set_option(dns.OPT_MODE_TILE, tile)
+    gpu.set_option(dns.OPT_CHAINS, chains)
+    gpu.set_option(dns.OPT_GRAPH, graph)
+    return gpu
+
+
+def sampled_report(gpu, ref, bar, abs_bar=None):
     v, eta, U, W = gpu.get_state()
+    got = tuple(a[PICK] for a in (v, eta, U, W))
     lam = ref.laminar_profile()[None, :]
-    errs = {"v": rel(v[pick], ref.v), "eta": rel(eta[pick], ref.eta),
-            "U-Ulam": rel(U[pick] - lam, ref.U - lam), "W": rel(W[pick], ref.W)}
+    if abs_bar is None:
+        return state_report(got, (ref.v, ref.eta, ref.U, ref.W), lam, bar)
+    rep = state_report(got, (ref.v, ref.eta, ref.U, ref.W), lam, bar)
+    rep["v/check"] = mode_check(got[0], ref.v, bar, abs_bar)[0]
+    rep["eta/check"] = mode_check(got[1], ref.eta, bar, abs_bar)[0]
+    rep["U/check"] = profile_check(got[2] - lam, ref.U - lam, bar, abs_bar)[0]
+    rep["W/check"] = profile_check(got[3], ref.W, bar, abs_bar)[0]
+    return rep
+
+
+def test_parity_channel_64x97x64_sampled_members_3_steps_fp64():
+    """Full size, 16 members, FP64, graph and two member chains; members 0
+    and 15 against the oracle after 3 steps."""
+    say("case: channel 64x97x64 E=16 FP64 graph 2 chains, 3 steps, members 0 and 15 vs oracle")
+    st = inputs.workload_state(HEADLINE)
+    gpu = headline_ensemble(dns.PREC_FP64, graph=1, chains=2)
+    gpu.set_state(*st)
+    gpu.step(3)
+    ref = headline_sample_oracle(st, 3)
+    errs = sampled_report(gpu, ref, 1e-10)
     say("errors:", errs)
-    for k, e in errs.items():
-        assert e <= 1e-10, (k, e)
+    assert_state(errs, 1e-10)
     # the other members stayed finite and held the flux
     s = gpu.stats()
     assert not s["failed"].any()
     np.testing.assert_allclose(s["flux"], 4.0 / 3.0, rtol=1e-12)
     gpu.close()
+
+
+def test_headline_configuration_end_to_end():
+    """The benchmark's exact configuration: channel Re 4200, 64x97x64, 16
+    members, advective form, mixed precision, hipGraph, two member chains,
+    32-row plane chunks and 4-member mode tiles.
+    (1) Graph + chains is bitwise the eager single-chain run with the same
+        tiles, over 4 steps.
+    (2) Members 0 and 15 against the FP64 oracle after 4 steps, per field and
+        per mode: bar 2e-6 relative plus 1e-7 of the largest mode (FP32
+        transforms and stage buffers, about 2^-24 per rounding).
+    (3) All 16 members against the GPU's own FP64 run, same bars."""
+    say("case: headline configuration, channel 64x97x64 E=16 mixed graph 2 chains rows 32 tile 4, 4 steps")
+    st = inputs.workload_state(HEADLINE)
+    steps = 4
+    bench = headline_ensemble(dns.PREC_MIXED_FP32, graph=1, chains=2, rows=32, tile=4)
+    bench.set_state(*st)
+    bench.step(steps)
+    got = bench.get_state()
+    eager = headline_ensemble(dns.PREC_MIXED_FP32, graph=0, chains=1, rows=32, tile=4)
+    eager.set_state(*st)
+    for _ in range(steps):
+        eager.step(1)
+    for a, b in zip(got, eager.get_state()):
+        assert np.array_equal(a, b)
+    eager.close()
+    ref = headline_sample_oracle(st, steps)
+    errs = sampled_report(bench, ref, 2e-6, abs_bar=1e-7)
+    say("mixed vs FP64 oracle, members 0 and 15:", errs)
+    assert_state(errs, 2e-6)
+    fp64 = headline_ensemble(dns.PREC_FP64, graph=1, chains=2)
+    fp64.set_state(*st)
+    fp64.step(steps)
+    ref64 = fp64.get_state()
+    lam = ref.laminar_profile()[None, :]
+    rep = state_report(got, ref64, lam, 2e-6)
+    rep["v/check"] = mode_check(got[0], ref64[0], 2e-6, 1e-7)[0]
+    rep["eta/check"] = mode_check(got[1], ref64[1], 2e-6, 1e-7)[0]
+    rep["U/check"] = profile_check(got[2] - lam, ref64[2] - lam, 2e-6, 1e-7)[0]
+    rep["W/check"] = profile_check(got[3], ref64[3], 2e-6, 1e-7)[0]
+    say("mixed vs FP64 GPU, all members:", rep)
+    assert_state(rep, 2e-6)
+    s = bench.stats()
+    assert not s["failed"].any()
+    np.testing.assert_allclose(s["flux"], 4.0 / 3.0, rtol=1e-12)
+    for h in (bench, fp64):
+        h.close()
 
 
 def test_parity_channel_72x73x72_fp64():
@@ -215,8 +291,7 @@ def test_parity_channel_72x73x72_fp64():
     ref.step(3)
     errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
     say("errors:", errs)
-    for k, e in errs.items():
-        assert e <= 1e-10, (k, e)
+    assert_state(errs, 1e-10)
     with pytest.raises(dns.DnsError):        # no FP64 quasi-linear variant fits this grid
         gpu.set_option(dns.OPT_QUASILINEAR, 1)
     gpu.close()
@@ -257,6 +332,27 @@ def test_state_roundtrip_and_validation():
     assert ei.value.code == dns.DNS_E_INVALID
     with pytest.raises(dns.DnsError):
         gpu.get_state(2, 5)
+    # the rules of dns_check_state, for host and device views; a rejected call
+    # leaves the state as it was
+    before = gpu.get_state()
+    import torch
+    for what in ("nan_wall", "herm", "zero_mode"):
+        v, eta, U, W = (a.copy() for a in st)
+        if what == "nan_wall":
+            U[2, -1] = np.nan
+        elif what == "herm":
+            eta[1, 0, 3, 7] += 0.5
+        else:
+            v[0, 0, 0, 0] = 0.25
+        with pytest.raises(dns.DnsError) as ei:
+            gpu.set_state(v, eta, U, W)
+        assert ei.value.code == dns.DNS_E_INVALID
+        dev = [torch.from_numpy(a).to("cuda") for a in (v, eta, U, W)]
+        with pytest.raises(dns.DnsError) as ei:
+            gpu.set_state_device(*dev)
+        assert ei.value.code == dns.DNS_E_INVALID
+    for a, b in zip(before, gpu.get_state()):
+        assert np.array_equal(a, b)
     gpu.close()
 
 
@@ -363,6 +459,20 @@ def test_time_averaged_statistics_match_oracle():
     for k in ("U", "urms", "vrms", "wrms", "uv"):
         assert np.abs(s[k] - r[k]).max() <= 1e-11 * max(1.0, np.abs(r[k]).max()), k
     np.testing.assert_allclose(s["tau_w"], r["tau_w"], rtol=1e-11)
+    # per-member time averages, the inputs of a bootstrap over members
+    mp = s["member_profiles"]
+    want_all = {k: acc.sums[k] / acc.n for k in ("U", "W", "U2", "W2", "vv", "uv")}
+    want_all["uu"] = (acc.sums["uu"] + acc.sums["U2"]) / acc.n    # plane means, mean flow included
+    want_all["ww"] = (acc.sums["ww"] + acc.sums["W2"]) / acc.n
+    for q, k in enumerate(gpu.MEMBER_PROFILES):
+        want = want_all[k]
+        assert np.abs(mp[:, q] - want).max() <= 1e-11 * max(1.0, np.abs(want).max()), k
+    np.testing.assert_allclose(s["member_tau"][:, 0], acc.sums["dUlo"] / acc.n / ref.Re, rtol=1e-11)
+    np.testing.assert_allclose(s["member_tau"][:, 1], acc.sums["dUhi"] / acc.n / ref.Re, rtol=1e-11)
+    # pooling them reproduces the ensemble statistics
+    Ubar = mp[:, 0].mean(axis=0)
+    np.testing.assert_allclose(np.sqrt(np.maximum(mp[:, 4].mean(axis=0) - Ubar ** 2, 0)),
+                               s["urms"], rtol=1e-10, atol=1e-7)
     gpu.close()
 
 
@@ -382,5 +492,5 @@ def test_mixed_precision_error_is_small(precision):
     say("mixed errors after 100 steps:", errs)
     split = precision == dns.PREC_MIXED_3XBF16
     assert max(e_stage.values()) <= (1e-4 if split else 1e-5)
-    assert max(errs.values()) <= (1e-3 if split else 1e-4)
+    assert max(errs[k] for k in ("v", "eta", "U-Ulam", "W")) <= (1e-3 if split else 1e-4)
     gpu.close()
