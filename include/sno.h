@@ -60,6 +60,24 @@ int dns_get_channels(dns_handle* h, int member0, int count, float* out);
  * Clears the members' failure flags.  Synchronises.  Errors as above. */
 int dns_set_channels(dns_handle* h, int member0, int count, const float* in);
 
+/* Allocation-free dns_set_channels, for callers that cannot allocate device
+ * memory during the call (work captured into a HIP graph, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments and the same resulting
+ * states, bitwise, as dns_set_channels.  It calls no allocating routine: its
+ * FP64 intermediates (per member 3 Ny planes of Mx Mz values and 3 Ny x
+ * Nx/2 (Nz-1) complex values) live in a fixed library array of
+ * DNS_NOALLOC_SCRATCH_BYTES on each GPU, held until the process ends.
+ * It queues its kernels on the handle's stream and returns without
+ * synchronising (the failure flags are cleared by a kernel, not a memset);
+ * `in` must stay valid until that work has run.  All calls on one GPU, from
+ * every handle, share that array and leave the last call's intermediates in
+ * it: calls whose queued work overlaps in time race, so order them (one
+ * stream, or events).  Errors: DNS_E_INVALID (range, NULL, or count above
+ * the members whose intermediates fit the array; the message gives that
+ * number), DNS_E_STATE, DNS_E_HIP. */
+#define DNS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int dns_set_channels_noalloc(dns_handle* h, int member0, int count, const float* in);
+
 typedef struct sno_handle sno_handle;
 
 typedef struct {

@@ -27,6 +27,8 @@
 
 using namespace dns;
 
+static_assert(kNoAllocScratchBytes == DNS_NOALLOC_SCRATCH_BYTES, "scratch size of the header and the library");
+
 struct dns_handle {
   // problem
   int flow = 0;
@@ -84,6 +86,7 @@ struct dns_handle {
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
   double max_cond = 0.0;
+  int device = 0;  // the device current at creation
   std::string err;
   // grouped handle: ensembles of different grid, Re, box or dt advanced by one
   // dns_step (members numbered group-major); each group runs on its own stream,
@@ -162,6 +165,31 @@ void free_all(dns_handle* h) {
     if (h->Dlo[i]) hipFree(h->Dlo[i]);
   }
   if (h->own_stream) hipStreamDestroy(h->own_stream);
+}
+
+// Chebyshev interpolation on the ascending nodes y_j = -cos(pi j / n), n = My - 1:
+// T_k(y_j) = (-1)^k cos(pi k j / n); coefficients by the discrete cosine
+// (DCT-I) orthogonality, a_k = 2 / (n c_k) sum_j T_k(y_j) f_j / c_j, c_0 = c_n = 2.
+int ensure_cheb(dns_handle* h) {
+  if (h->cheb_cinv) return DNS_OK;
+  const int My = h->My, n = My - 1;
+  std::vector<double> T(size_t(My) * My), Ci(size_t(My) * My);
+  auto Tk = [&](int k, int j) {
+    const long long r = (long long)k * j % (2 * n);
+    return ((k & 1) ? -1.0 : 1.0) * std::cos(M_PI * double(r) / n);
+  };
+  for (int j = 0; j < My; ++j)
+    for (int k = 0; k < My; ++k) T[size_t(j) * My + k] = Tk(k, j);
+  for (int k = 0; k < My; ++k)
+    for (int j = 0; j < My; ++j) {
+      const double ck = (k == 0 || k == n) ? 2.0 : 1.0, cj = (j == 0 || j == n) ? 2.0 : 1.0;
+      Ci[size_t(k) * My + j] = 2.0 / (n * ck) * Tk(k, j) / cj;
+    }
+  if (dalloc(&h->cheb_cinv, Ci.size()) != hipSuccess || dalloc(&h->cheb_t, T.size()) != hipSuccess)
+    return fail(h, DNS_E_NOMEM, "hipMalloc Chebyshev matrices");
+  HIP_OR_FAIL(h, hipMemcpy(h->cheb_cinv, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice));
+  HIP_OR_FAIL(h, hipMemcpy(h->cheb_t, T.data(), T.size() * 8, hipMemcpyHostToDevice));
+  return DNS_OK;
 }
 
 int ensure_staging(dns_handle* h, size_t bytes) {
@@ -745,6 +773,15 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess)
     return fail_free(DNS_E_HIP, "hipStreamCreate");
   h->stream = h->own_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) return fail_free(DNS_E_HIP, "hipGetDevice");
+  // the allocation-free hand-off needs this device's scratch address and the
+  // Chebyshev tables of the channel form, so both exist from creation on
+  if (noalloc_scratch_init(h->device) != hipSuccess)
+    return fail_free(DNS_E_HIP, "looking up the allocation-free scratch");
+  {
+    const int rc = ensure_cheb(h);
+    if (rc != DNS_OK) return fail_free(rc, h->err);
+  }
   // every kernel a step uses is resolved now, so that no captured step holds a
   // kernel's first launch
   if (plane_preload(Nx) != hipSuccess || mode_preload() != hipSuccess || misc_preload() != hipSuccess)
@@ -1655,34 +1692,6 @@ int dns_tune(dns_handle* h, const char* cache_path, dns_tuning* out) {
   return tune_one(h, cache_path, out);
 }
 
-namespace {
-
-// Chebyshev interpolation on the ascending nodes y_j = -cos(pi j / n), n = My - 1:
-// T_k(y_j) = (-1)^k cos(pi k j / n); coefficients by the discrete cosine
-// (DCT-I) orthogonality, a_k = 2 / (n c_k) sum_j T_k(y_j) f_j / c_j, c_0 = c_n = 2.
-int ensure_cheb(dns_handle* h) {
-  if (h->cheb_cinv) return DNS_OK;
-  const int My = h->My, n = My - 1;
-  std::vector<double> T(size_t(My) * My), Ci(size_t(My) * My);
-  auto Tk = [&](int k, int j) {
-    const long long r = (long long)k * j % (2 * n);
-    return ((k & 1) ? -1.0 : 1.0) * std::cos(M_PI * double(r) / n);
-  };
-  for (int j = 0; j < My; ++j)
-    for (int k = 0; k < My; ++k) T[size_t(j) * My + k] = Tk(k, j);
-  for (int k = 0; k < My; ++k)
-    for (int j = 0; j < My; ++j) {
-      const double ck = (k == 0 || k == n) ? 2.0 : 1.0, cj = (j == 0 || j == n) ? 2.0 : 1.0;
-      Ci[size_t(k) * My + j] = 2.0 / (n * ck) * Tk(k, j) / cj;
-    }
-  if (dalloc(&h->cheb_cinv, Ci.size()) != hipSuccess || dalloc(&h->cheb_t, T.size()) != hipSuccess)
-    return fail(h, DNS_E_NOMEM, "hipMalloc Chebyshev matrices");
-  HIP_OR_FAIL(h, hipMemcpy(h->cheb_cinv, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice));
-  HIP_OR_FAIL(h, hipMemcpy(h->cheb_t, T.data(), T.size() * 8, hipMemcpyHostToDevice));
-  return DNS_OK;
-}
-
-}  // namespace
 
 int dns_get_channels(dns_handle* h, int member0, int count, float* out) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
@@ -1734,6 +1743,37 @@ int dns_set_channels(dns_handle* h, int member0, int count, const float* in) {
   if (h->shared_mean)
     HIP_OR_FAIL(h, launch_share_columns(h->v, h->eta, h->U, h->W, h->E, h->N, h->NZ, h->My, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  h->vel_fresh = false;
+  return DNS_OK;
+}
+
+int dns_set_channels_noalloc(dns_handle* h, int member0, int count, const float* in) {
+  if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
+  ORDER_AFTER_PARENT(h);
+  if (h->grouped()) {
+    dns_handle* sh;
+    int m0;
+    const int rc = route(h, member0, count, &sh, &m0);
+    return rc ? rc : forward(h, sh, dns_set_channels_noalloc(sh, m0, count, in));
+  }
+  if (!in) return fail(h, DNS_E_INVALID, "in is NULL");
+  if (member0 < 0 || count < 1 || member0 + count > h->E) return fail(h, DNS_E_INVALID, "member range out of bounds");
+  const int Mx = 3 * h->Nx / 2, Mz = 3 * h->Nz / 2;
+  const size_t per_member = size_t(3) * h->My * (size_t(Mx) * Mz + 2 * size_t(h->K));
+  const size_t max_count = kNoAllocScratchBytes / (per_member * sizeof(double));
+  if (size_t(count) > max_count)
+    return fail(h, DNS_E_INVALID,
+                "count " + std::to_string(count) + " exceeds the allocation-free scratch (" +
+                    std::to_string(kNoAllocScratchBytes >> 20) + " MiB): at most " + std::to_string(max_count) +
+                    " members per call on this grid");
+  double* scr = noalloc_scratch(h->device);
+  if (!scr || !h->cheb_t) return fail(h, DNS_E_STATE, "allocation-free scratch not set up on this device");
+  const size_t nphys = size_t(count) * 3 * h->My * Mx * Mz;
+  HIP_OR_FAIL(h, launch_from_channels(in, scr, scr + nphys, h->cheb_t, h->v, h->eta, h->U, h->W, h->My, h->E, h->L,
+                                      h->NZ, Mx, Mz, member0, count, h->kxs, h->kzs, h->Ubot, h->Utop, h->stream));
+  HIP_OR_FAIL(h, launch_clear_ints(h->failed + member0, count, h->stream));
+  if (h->shared_mean)
+    HIP_OR_FAIL(h, launch_share_columns(h->v, h->eta, h->U, h->W, h->E, h->N, h->NZ, h->My, h->stream));
   h->vel_fresh = false;
   return DNS_OK;
 }

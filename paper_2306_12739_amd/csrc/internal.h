@@ -196,6 +196,15 @@ hipError_t launch_from_channels(const float* in, double* phys, double* spec, con
                                 double* eta, double* U, double* W, int My, int E, int L, int NZ, int Mx, int Mz,
                                 int member0, int count, double kxs, double kzs, double Ubot, double Utop,
                                 hipStream_t s);
+// Fixed per-device scratch of the allocation-free hand-off (a __device__ array
+// of kNoAllocScratchBytes).  noalloc_scratch_init looks up its address on
+// `device`, which must be current, once per device; noalloc_scratch returns
+// that address (nullptr before the lookup).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch_init(int device);
+double* noalloc_scratch(int device);
+// p[0..n) = 0 by a kernel (no memset node in a captured stream)
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s);
 
 // ---- spectral neural operator (learned spin-up) --------------------------------
 // C[b][m][n] = alpha * sum_k A[b][m][k] B[b][k][n] + beta * C[b][m][n]; element

@@ -12,6 +12,8 @@
 // (member, field, node)); they run once per hand-off, not per time step.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace dns {
@@ -189,7 +191,49 @@ int grid_of(long long n) {
   return int(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
+__global__ void clear_ints_kernel(int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
+
+// ---- scratch of the allocation-free hand-off -----------------------------------
+// dns_set_channels_noalloc keeps its FP64 intermediates in this fixed array
+// instead of the handle's staging buffer.  Every GPU the library runs on holds
+// its own copy until the process ends.  In host code the array's name is only a
+// stand-in: the device address comes from hipGetSymbolAddress, looked up once
+// per device (with that device current) and kept in g_scratch_ptr.
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (err != hipSuccess) return err;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return static_cast<double*>(g_scratch_ptr[device]);
+}
+
+hipError_t launch_clear_ints(int* p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(clear_ints_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_to_channels(int precision, const void* vel, double* phys, const double* cinv, float* out, int My,
                               int E, int K, int L, int NZ, int Mx, int Mz, int member0, int count, hipStream_t s) {

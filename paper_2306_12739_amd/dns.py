@@ -53,7 +53,7 @@ EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "d
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",
             "dns_debug_stage0", "dns_kernel_times", "dns_host_operators",
             "dns_create_grouped", "dns_group_handle", "dns_tune",
-            "dns_get_channels", "dns_set_channels", "dns_set_forcing",
+            "dns_get_channels", "dns_set_channels", "dns_set_channels_noalloc", "dns_set_forcing",
             "dns_perturbation_energy", "dns_orthonormalize", "dns_check_state",
             "sno_create", "sno_set_option", "sno_num_params", "sno_set_params", "sno_get_params",
             "sno_forward", "sno_loss_grad", "sno_train_step", "sno_sync", "sno_last_error",
@@ -152,6 +152,7 @@ def library(path=LIB_PATH):
     lib.dns_tune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(Tuning)]
     lib.dns_get_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     lib.dns_set_channels.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.dns_set_channels_noalloc.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
     lib.dns_set_forcing.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int]
     lib.dns_perturbation_energy.argtypes = [vp, _DP]
     lib.dns_orthonormalize.argtypes = [vp]
@@ -378,6 +379,12 @@ class Ensemble:
         """Rebuild members' states from channel-form data (float32 CUDA tensor)."""
         self._check_channels(x)
         return self._check(self.lib.dns_set_channels(self.h, member0, x.shape[0], x.data_ptr()))
+
+    def set_channels_noalloc(self, x, member0=0):
+        """As set_channels, without allocating: intermediates in the library's
+        fixed per-GPU scratch; queued on the handle's stream, not synchronised."""
+        self._check_channels(x)
+        return self._check(self.lib.dns_set_channels_noalloc(self.h, member0, x.shape[0], x.data_ptr()))
 
     def _check_channels(self, t):
         P = (3 * self.Nx // 2) * (3 * self.Nz // 2)

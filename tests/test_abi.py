@@ -59,6 +59,8 @@ def test_null_handle_calls_are_rejected():
     assert lib.dns_sync(None) == dns.DNS_E_STATE
     assert lib.dns_stats(None, None) == dns.DNS_E_STATE
     assert lib.dns_set_option(None, dns.OPT_PRECISION, 0) == dns.DNS_E_STATE
+    assert lib.dns_set_channels(None, 0, 1, None) == dns.DNS_E_STATE
+    assert lib.dns_set_channels_noalloc(None, 0, 1, None) == dns.DNS_E_STATE
     lib.dns_destroy(None)   # NULL-safe
 
 
