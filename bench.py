@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # The published FP32 vector figure counts packed (two-wide) FP32 FMAs.
 FP32_PUBLISHED_TFLOPS = 157.3
+METRIC = "ensemble member-steps/s at Re_tau~180; mixed vs FP64 at <=1% stats error"
 
 
 def parse():
@@ -55,6 +56,10 @@ def parse():
                          "timed briefly on the same ensemble and reported beside it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--steps-only", action="store_true",
+                    help="time the headline steps only and print the line without the per-kernel, "
+                         "FP64, other-form, serial and CPU figures (for kernel traces whose last "
+                         "dispatches are the timed steps)")
     return ap.parse_args()
 
 
@@ -95,18 +100,22 @@ def kernel_model(w, E, precision, form="advective"):
     return {"plane": (plane_bytes, plane_flops), "mode": (mode_bytes, mode_flops)}
 
 
-def source_hash():
+def source_hash(files):
+    """Hash of the named files under paper_2306_12739_amd/csrc (the sources of
+    one kernel), in the order given."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2306_12739_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in files:
+        p = os.path.join(csrc, f)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload, precision):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, only if
-    they were taken on the current kernel sources."""
+    """HBM bytes per launch from the committed rocprofv3 counter record, only
+    if it was taken on the current sources of that kernel."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -114,10 +123,10 @@ def measured_traffic(kernel, workload, precision):
         d = json.load(open(path))
     except ValueError:
         return None
-    if d.get("source_hash") != source_hash():
-        return None
     rec = d.get("kernels", {}).get(f"{kernel}/{workload}/{precision}")
-    return None if rec is None else rec.get("bytes_per_launch")
+    if rec is None or rec.get("source_hash") != source_hash(rec.get("sources", [])):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def host_cpu():
@@ -270,6 +279,12 @@ def main():
     s = ens.stats(allow_nonfinite=True)
     if s["rc"] != 0:
         print(f"warning: {int(s['failed'].sum())} members non-finite", file=sys.stderr)
+    if args.steps_only:
+        ens.close()
+        print(json.dumps({"metric": METRIC, "value": E * args.steps / (ms / 1e3), "unit": "member-steps/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": ms / args.steps, "steps_only": True, "tuning": tuning}), flush=True)
+        return
 
     plane_ms, mode_ms = ens.kernel_times(args.kernel_reps)
     # the other advection form, briefly, on the same ensemble (tuned for itself)
@@ -332,7 +347,7 @@ def main():
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, name)
     out = {
-        "metric": "ensemble member-steps/s at Re_tau~180; mixed vs FP64 at <=1% stats error",
+        "metric": METRIC,
         "value": value,
         "unit": "member-steps/s",
         "n_gpus": 1,

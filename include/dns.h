@@ -110,9 +110,15 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
 #define DNS_OPT_GRAPH 3       /* value: 1 capture one step as a hipGraph, 0 eager;
                                  DNS_E_UNSUPPORTED for 1 on a grouped handle     */
 #define DNS_OPT_STATS 4       /* value: 1 accumulate one-point statistics each step */
-#define DNS_OPT_PLANE_ROWS 5  /* value: physical z rows per chunk of the advection
-                                 kernel, one of the built variants (DNS_E_UNSUPPORTED
-                                 otherwise); applies to the current precision   */
+#define DNS_OPT_PLANE_ROWS 5  /* value: advection-kernel variant, one of the built
+                                 ones (DNS_E_UNSUPPORTED otherwise), for the current
+                                 precision and advection form: the physical z rows
+                                 per chunk of the general kernel, or, for the
+                                 advective form on grids with Nx = Nz = 32 or 64,
+                                 100 + rows (+ 50 when its forward-z sums are kept
+                                 in the output buffer instead of registers) for
+                                 the lane-parallel x-transform kernel, which is
+                                 the default there                              */
 #define DNS_OPT_MODE_TILE 6   /* value: members per workgroup of the per-mode kernel,
                                  1, 2, 4 or 8, fitting 160 KB of LDS           */
 #define DNS_OPT_CHAINS 7      /* value: 1..DNS_MAX_CHAINS (<= ensemble): the members

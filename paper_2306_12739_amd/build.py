@@ -19,7 +19,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdns_ensemble.so")
 
-SOURCES = ["kernels_plane.hip", "kernels_mode.hip", "kernels_misc.hip", "kernels_channels.hip",
+SOURCES = ["kernels_plane.hip", "kernels_plane_wave.hip", "kernels_mode.hip", "kernels_misc.hip", "kernels_channels.hip",
            "kernels_sno.hip", "operators.cpp", "dns_api.cpp", "sno.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -326,7 +326,7 @@ PlaneArgs plane_args(dns_handle* h, bool sums, int e0 = 0, int ec = -1, bool wal
 int plane_form(const dns_handle* h) { return h->quasilinear ? 1 + h->quasilinear : h->advection; }
 // some (form, precision) pairs have no chunk variant within the LDS of the larger grids
 bool form_fits(const dns_handle* h, int precision, int form) {
-  int rows[3];
+  int rows[kMaxPlaneVariants];
   return plane_variants(precision == DNS_PREC_FP64 ? 0 : 1, form, h->Nx, rows) > 0;
 }
 
@@ -938,7 +938,7 @@ int dns_set_option(dns_handle* h, int key, long long value) {
       return DNS_OK;
     case DNS_OPT_PLANE_ROWS: {
       if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
-      int rows[3];
+      int rows[kMaxPlaneVariants];
       const int n = plane_variants(h->precision, plane_form(h), h->Nx, rows);
       for (int v = 0; v < n; ++v)
         if (rows[v] == value) {
@@ -1630,7 +1630,7 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
     const int rc = refresh_velocities(h);
     if (rc) return rc;
   }
-  int rows[3];
+  int rows[kMaxPlaneVariants];
   const int nv = plane_variants(h->precision, plane_form(h), h->Nx, rows);
   int best_v = 0;
   double best_p = 1e30;

@@ -96,9 +96,20 @@ struct ModeArgs {
 constexpr int kPlaneForms = 4;
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s);
-// Chunk-row counts of the plane-kernel variants built for (precision, form,
-// Nx); returns how many (<= 3), index 0 being the default.
+// Plane-kernel variants built for (precision, form, Nx), index 0 being the
+// default: returns how many (<= kMaxPlaneVariants).  rows[v] is the chunk-row
+// count of variant v, plus kWaveRows for the lane-parallel advective kernel.
+constexpr int kMaxPlaneVariants = 12;
+constexpr int kWaveRows = 100;
+constexpr int kWaveGlobalAcc = 50;
 int plane_variants(int precision, int form, int Nx, int* rows);
+// Lane-parallel advective kernel (kernels_plane_wave.hip): the kernel of
+// (precision, grid, code) or nullptr, where code is the chunk-row count plus
+// kWaveGlobalAcc for the variant whose forward-z sums live in the output
+// buffer; the built codes (default first); the workgroup size of a code.
+const void* plane_wave_fn(int precision, int Nx, int Nz, int code);
+int plane_wave_rows(int precision, int Nx, int Nz, int* codes);
+int plane_wave_threads(int Nx, int code);
 bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
 // Resolve kernels on the current device before any graph capture uses them.

@@ -595,10 +595,11 @@ bool plane_supported(int Nx, int Nz) {
 hipError_t plane_preload(int Nx) {
   for (int prec = 0; prec < 2; ++prec) {
     for (int form = 0; form < kPlaneForms; ++form) {
-      int rows[3];
+      int rows[kMaxPlaneVariants];
       const int n = plane_variants(prec, form, Nx, rows);  // 0: this form does not fit this grid
       for (int v = 0; v < n; ++v) {
-        const void* fn = plane_fn(prec, form, Nx, rows[v]);
+        const void* fn = rows[v] > kWaveRows ? plane_wave_fn(prec, Nx, Nx, rows[v] - kWaveRows)
+                                             : plane_fn(prec, form, Nx, rows[v]);
         if (!fn) return hipErrorInvalidValue;
         hipFuncAttributes attr;
         const hipError_t err = hipFuncGetAttributes(&attr, fn);
@@ -609,12 +610,18 @@ hipError_t plane_preload(int Nx) {
   return hipSuccess;
 }
 
-// The table's variants that are built for this form (the quasi-linear form
-// needs more LDS and drops the largest chunks).
+// The lane-parallel advective variants first (advective form, grids with a
+// power-of-two Nx/2), then the table's variants that are built for this form
+// (the quasi-linear form needs more LDS and drops the largest chunks).
 int plane_variants(int precision, int form, int Nx, int* rows) {
+  int n = 0;
+  if (form == 0) {
+    int wave[6];
+    const int nw = plane_wave_rows(precision, Nx, Nx, wave);
+    for (int v = 0; v < nw; ++v) rows[n++] = kWaveRows + wave[v];
+  }
   int all[3];
   const int n_all = table_rows(precision, Nx, all);
-  int n = 0;
   for (int v = 0; v < n_all; ++v)
     if (plane_fn(precision, form, Nx, all[v])) rows[n++] = all[v];
   return n;
@@ -626,13 +633,16 @@ int plane_variants(int precision, int form, int Nx, int* rows) {
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s) {
   if (!plane_supported(Nx, Nz) || form < 0 || form >= kPlaneForms) return hipErrorInvalidValue;
-  int rows[3];
+  int rows[kMaxPlaneVariants];
   const int n = plane_variants(precision, form, Nx, rows);
   if (variant < 0 || variant >= n) return hipErrorInvalidValue;
-  const void* fn = plane_fn(precision, form, Nx, rows[variant]);
+  const bool wave = rows[variant] > kWaveRows;
+  const void* fn = wave ? plane_wave_fn(precision, Nx, Nz, rows[variant] - kWaveRows)
+                        : plane_fn(precision, form, Nx, rows[variant]);
   if (!fn) return hipErrorInvalidValue;
+  const int nt = wave ? plane_wave_threads(Nx, rows[variant] - kWaveRows) : kNT;
   void* args[] = {const_cast<PlaneArgs*>(&a)};
-  const hipError_t err = hipLaunchKernel(fn, dim3(a.nj * a.ec), dim3(kNT), args, 0, s);
+  const hipError_t err = hipLaunchKernel(fn, dim3(a.nj * a.ec), dim3(nt), args, 0, s);
   return err != hipSuccess ? err : hipGetLastError();
 }
 

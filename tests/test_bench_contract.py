@@ -53,7 +53,10 @@ def test_mode_kernel_flops_count_every_half_size_product():
 
 
 def test_source_hash_is_stable_and_vector_peak_is_the_unpacked_rate():
-    h1, h2 = bench.source_hash(), bench.source_hash()
+    files = ["kernels_plane_wave.hip", "fft.h", "internal.h"]
+    h1, h2 = bench.source_hash(files), bench.source_hash(files)
     assert h1 == h2 and len(h1) == 16
     assert int(h1, 16) >= 0
+    assert bench.source_hash(files[:1]) != h1          # depends on every listed file
+    assert bench.source_hash(["no_such_file.hip"]) is None
     assert np.isfinite(bench.VALU_PEAK_TFLOPS) and abs(bench.VALU_PEAK_TFLOPS - 78.6432) < 1e-9

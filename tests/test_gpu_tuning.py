@@ -23,10 +23,14 @@ GRIDS = [  # (flow, Re, Lx, Lz, N, Ny, dt, amplitude)
     (1, 4200.0, 2.0 * np.pi, np.pi, 64, 97, 0.005, 0.3),
     (1, 4200.0, 2.0 * np.pi, np.pi, 72, 73, 0.005, 0.3),
 ]
-ROWS = {  # built variants, default first
-    dns.PREC_FP64: {16: [24, 12, 8], 32: [16, 24, 8], 48: [12, 8], 64: [16, 12, 8], 72: [12]},
-    dns.PREC_MIXED_FP32: {16: [24, 12, 8], 32: [16, 24, 48], 48: [12, 24, 36], 64: [32, 24, 16],
-                          72: [18, 12]},
+# built variants, default first: chunk rows of the general kernel, and 100 +
+# chunk rows (+ 50 with the forward-z sums kept in the output buffer) of the
+# lane-parallel advective kernel
+ROWS = {
+    dns.PREC_FP64: {16: [24, 12, 8], 32: [116, 166, 148, 198, 16, 24, 8], 48: [12, 8],
+                    64: [166, 116, 16, 12, 8], 72: [12]},
+    dns.PREC_MIXED_FP32: {16: [24, 12, 8], 32: [116, 166, 148, 198, 16, 24, 48], 48: [12, 24, 36],
+                          64: [182, 116, 166, 132, 32, 24, 16], 72: [18, 12]},
 }
 
 
