@@ -61,7 +61,10 @@ typedef struct {
 
 /* Create an ensemble solver (Sec. 3.2: operators are built once per (kx,kz) and
  * h in {1/2, 1}, on the host in extended precision, then uploaded).
- *   Nx, Nz : 16, 32, 48, 64 or 72 with Nx == Nz;  Ny : 5..252 (odd or even);
+ *   Nx, Nz : 16, 32, 48, 64, 72 or 96 with Nx == Nz, or (Nx, Nz) = (64, 32)
+ *            or (32, 64) (advective form only: DNS_OPT_ADVECTION and
+ *            DNS_OPT_QUASILINEAR then return DNS_E_UNSUPPORTED);
+ *            Ny : 5..252 (odd or even);
  *   ensemble >= 1; dt > 0; Re > 0.
  * The state is initialised to the laminar profile (Couette U = Uw y, channel
  * U = 1 - y^2) with zero perturbations.  Device memory is owned by the handle.
@@ -73,12 +76,13 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
 /* Several ensembles advanced together (Sec. 3.2 batches members of one
  * configuration; here independent configurations -- different Re, grid, box,
  * dt or flow -- share one dns_step).  Each group is a full ensemble as made by
- * dns_create, with its own operators and buffers; its kernels run on a stream
- * of its own, forked from and joined back into the grouped handle's stream
- * (launched eagerly: DNS_OPT_GRAPH = 1 on a grouped handle returns
- * DNS_E_UNSUPPORTED), so small groups overlap on the device.  Members are
- * numbered group-major: group g holds members [sum of earlier groups' members,
- * + members).
+ * dns_create, with its own operators and buffers.  Each sub-step runs the
+ * groups' advection kernels on streams of their own (forked from and joined
+ * back into the grouped handle's stream) and then one per-mode launch over
+ * every group (DNS_OPT_GROUP_STREAMS selects per-group streams for the whole
+ * step instead).  Grouped steps run eagerly: DNS_OPT_GRAPH = 1 on a grouped
+ * handle returns DNS_E_UNSUPPORTED.  Members are numbered group-major: group g
+ * holds members [sum of earlier groups' members, + members).
  *   groups  : ngroups descriptions, 1 <= ngroups <= DNS_MAX_GROUPS; read only
  *             during the call.
  * On a grouped handle: dns_set_state / dns_get_state take member ranges inside
@@ -128,7 +132,9 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  advection kernel overlaps another's per-mode
                                  kernel.  Results do not depend on it.  Default:
                                  2 for ensembles of 8 or more members, else 1. */
-#define DNS_OPT_ADVECTION 8   /* value: DNS_ADV_*, the form of the advection term  */
+#define DNS_OPT_ADVECTION 8   /* value: DNS_ADV_*, the form of the advection term;
+                                 DNS_E_UNSUPPORTED if no variant of that form is
+                                 built for the grid at the current precision   */
 #define DNS_OPT_SHARED_MEAN 9 /* value: 1 the members share one streamwise-mean flow
                                  (approximate S3T ensemble, Sec. 4: the n_x = 0
                                  modes of v and eta and the profiles U00, W00),
@@ -158,6 +164,15 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  Default 0.                                     */
 #define DNS_OPT_V_DISCRETIZATION 12 /* value: DNS_VDISC_*; rebuilds the v operators
                                  on the host (long double) and reloads them   */
+#define DNS_OPT_GROUP_STREAMS 13 /* grouped handles only.  value 0 (default): each
+                                 sub-step runs every group's per-mode work
+                                 (right-hand sides, solves, velocities) in one
+                                 launch, a descriptor per group, after the
+                                 groups' advection kernels ran on their own
+                                 streams; 1: each group's whole step runs on a
+                                 stream of its own (also used while a group has
+                                 an external forcing).  Results do not depend
+                                 on it.                                         */
 
 /* Wall-normal discretizations of the v equation (Eq. (CN1)).  The paper uses
  * the fourth derivative of the clamped interpolant (Sec. 2).  The alternative

@@ -96,6 +96,16 @@ struct dns_handle {
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   dns_handle* parent = nullptr;
+  // grouped handle: every group's per-mode work in one launch per sub-step
+  // (descriptors [sub-step][group] and block offsets on the device, their host
+  // copy to detect changes); group_streams = true runs each group's kernels on
+  // its own stream instead
+  bool group_streams = false;
+  ModeArgs* gdesc = nullptr;
+  int* gfirst = nullptr;
+  std::vector<ModeArgs> gdesc_host;
+  std::vector<int> gfirst_host;
+  size_t glds = 0;
   bool grouped() const { return !sub.empty(); }
 };
 
@@ -157,7 +167,8 @@ void free_all(dns_handle* h) {
                   h->D1intT_e, h->D1intT_o, h->D1cT_e, h->D1cT_o, h->D1T_e, h->D1T_o,
                   h->lift_h[0], h->lift_h[1], h->green_h[0], h->green_h[1], h->ccw_h,
                   h->D1, h->ccw, h->cheb_cinv, h->cheb_t,
-                  h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging, h->fv, h->feta};
+                  h->gamma, h->failed, h->divmax, h->acc, h->inst, h->staging, h->fv, h->feta,
+                  h->gdesc, h->gfirst};
   for (void* p : bufs)
     if (p) hipFree(p);
   for (int i = 0; i < 6; ++i) {
@@ -327,7 +338,7 @@ int plane_form(const dns_handle* h) { return h->quasilinear ? 1 + h->quasilinear
 // some (form, precision) pairs have no chunk variant within the LDS of the larger grids
 bool form_fits(const dns_handle* h, int precision, int form) {
   int rows[kMaxPlaneVariants];
-  return plane_variants(precision == DNS_PREC_FP64 ? 0 : 1, form, h->Nx, rows) > 0;
+  return plane_variants(precision == DNS_PREC_FP64 ? 0 : 1, form, h->Nx, h->Nz, rows) > 0;
 }
 
 int& plane_var(dns_handle* h) { return h->plane_var[h->precision == DNS_PREC_FP64 ? 0 : 1][plane_form(h)]; }
@@ -467,7 +478,85 @@ int enqueue_grouped(dns_handle* h) {
   return DNS_OK;
 }
 
-int enqueue_any(dns_handle* h) { return h->grouped() ? enqueue_grouped(h) : enqueue_step(h); }
+// The grouped one-launch path applies unless asked for per-group streams, a
+// group carries an external forcing or the groups' precisions differ (a
+// group's own handle can set one).
+bool grouped_one_launch(const dns_handle* h) {
+  if (h->group_streams) return false;
+  for (const dns_handle* sh : h->sub)
+    if (sh->forcing_on || sh->precision != h->sub[0]->precision) return false;
+  return true;
+}
+
+// Per-mode descriptors of every group for the three sub-steps (each group's
+// full member range, its own tile shape), uploaded in stream order when they
+// differ from the last upload.
+int update_group_descs(dns_handle* h) {
+  const int ng = int(h->sub.size());
+  std::vector<ModeArgs> d(size_t(3) * ng);
+  std::vector<int> first(size_t(ng) + 1, 0);
+  size_t lds = 0;
+  for (int g = 0; g < ng; ++g) {
+    dns_handle* sh = h->sub[g];
+    for (int st = 0; st < 3; ++st) d[size_t(st) * ng + g] = mode_args(sh, st);
+    first[g + 1] = first[g] + sh->G * sh->ntiles;
+    lds = std::max(lds, size_t(2 * sh->SR + sh->TR) * sh->CRP * sizeof(double));
+  }
+  const bool same = h->gdesc_host.size() == d.size() &&
+                    std::memcmp(h->gdesc_host.data(), d.data(), d.size() * sizeof(ModeArgs)) == 0 &&
+                    h->gfirst_host == first;
+  if (same) return DNS_OK;
+  if (!h->gdesc) {
+    HIP_OR_FAIL(h, dalloc(&h->gdesc, d.size()));
+    HIP_OR_FAIL(h, dalloc(&h->gfirst, first.size()));
+  }
+  h->gdesc_host = d;
+  h->gfirst_host = first;
+  h->glds = lds;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->gdesc, h->gdesc_host.data(), d.size() * sizeof(ModeArgs), hipMemcpyHostToDevice,
+                                h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->gfirst, h->gfirst_host.data(), first.size() * sizeof(int),
+                                hipMemcpyHostToDevice, h->stream));
+  // the host copies must outlive the transfers
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  return DNS_OK;
+}
+
+// One step of every group with one per-mode launch per sub-step: each group's
+// advection work (and, at the first sub-step, its wall sums and diagnostics)
+// on the group's stream, forked from and joined into h->stream, then one
+// launch of the per-mode kernel over every group's workgroups on h->stream.
+int enqueue_grouped_one_launch(dns_handle* h) {
+  const int ng = int(h->sub.size());
+  const int nblk = h->gfirst_host[ng];
+  for (int st = 0; st < 3; ++st) {
+    HIP_OR_FAIL(h, hipEventRecord(h->fork, h->stream));
+    for (int g = 0; g < ng; ++g) {
+      dns_handle* sh = h->sub[g];
+      hipStream_t gs = sh->stream;
+      HIP_OR_FAIL(h, hipStreamWaitEvent(gs, h->fork, 0));
+      HIP_OR_FAIL(h, plane_launch(sh, st == 0, 0, sh->E, gs, false));
+      if (st == 0)
+        HIP_OR_FAIL(h, launch_wall_sums(sh->precision == DNS_PREC_FP64 ? 0 : 1, sh->vel, sh->psum, sh->means,
+                                        sh->My, sh->E, sh->K, sh->NZ, sh->P, sh->kxs, sh->kzs, 0, sh->E, gs));
+      if (sh->shared_mean)
+        HIP_OR_FAIL(h, launch_member_mean(sh->precision == DNS_PREC_FP64 ? 0 : 1, sh->nl, sh->means, sh->My, sh->E,
+                                          sh->K, sh->NZ, gs));
+      if (st == 0) HIP_OR_FAIL(h, launch_stats(stats_args(sh), sh->stats_on ? 1 : 0, gs));
+      HIP_OR_FAIL(h, hipEventRecord(h->join[g], gs));
+      HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->join[g], 0));
+    }
+    // every group has the precision of the grouped handle's options (set on all groups)
+    HIP_OR_FAIL(h, launch_mode_grouped(h->sub[0]->precision, false, h->gdesc + size_t(st) * ng, h->gfirst, ng, nblk,
+                                       h->glds, h->stream));
+  }
+  return DNS_OK;
+}
+
+int enqueue_any(dns_handle* h) {
+  if (!h->grouped()) return enqueue_step(h);
+  return grouped_one_launch(h) ? enqueue_grouped_one_launch(h) : enqueue_grouped(h);
+}
 
 int build_graph(dns_handle* h) {
   invalidate_graph(h);
@@ -629,7 +718,9 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   if (dc == DNS_E_INVALID)
     return fail(nullptr, dc, "need even Nx, Nz > 0, 5 <= Ny <= 257 and ensemble >= 1");
   if (dc == DNS_E_UNSUPPORTED)
-    return fail(nullptr, dc, "grid not built: Nx == Nz in {16, 32, 48, 64, 72} are supported");
+    return fail(nullptr, dc,
+                "grid not built: Nx == Nz in {16, 32, 48, 64, 72, 96}, and (Nx, Nz) = (64, 32) or (32, 64) "
+                "for the advective form, are supported");
   {
     // one member per per-mode workgroup must fit the workgroup LDS (Ny <= 252)
     int crp, sr, tr;
@@ -784,7 +875,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   }
   // every kernel a step uses is resolved now, so that no captured step holds a
   // kernel's first launch
-  if (plane_preload(Nx) != hipSuccess || mode_preload() != hipSuccess || misc_preload() != hipSuccess)
+  if (plane_preload(Nx, Nz) != hipSuccess || mode_preload() != hipSuccess || misc_preload() != hipSuccess)
     return fail_free(DNS_E_HIP, "resolving kernels");
   // two member chains overlap the advection and per-mode kernels of a step
   if (set_chains(h, h->E >= 8 ? 2 : 1) != DNS_OK) return fail_free(DNS_E_HIP, "creating chain streams");
@@ -936,10 +1027,15 @@ int dns_set_option(dns_handle* h, int key, long long value) {
       h->stats_on = value != 0;
       invalidate_graph(h);
       return DNS_OK;
+    case DNS_OPT_GROUP_STREAMS:
+      if (!h->grouped()) return fail(h, DNS_E_INVALID, "DNS_OPT_GROUP_STREAMS applies to grouped handles");
+      HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+      h->group_streams = value != 0;
+      return DNS_OK;
     case DNS_OPT_PLANE_ROWS: {
       if (h->grouped()) return fail(h, DNS_E_INVALID, "set tile shapes on a group's handle");
       int rows[kMaxPlaneVariants];
-      const int n = plane_variants(h->precision, plane_form(h), h->Nx, rows);
+      const int n = plane_variants(h->precision, plane_form(h), h->Nx, h->Nz, rows);
       for (int v = 0; v < n; ++v)
         if (rows[v] == value) {
           plane_var(h) = v;
@@ -960,6 +1056,8 @@ int dns_set_option(dns_handle* h, int key, long long value) {
         return fail(h, DNS_E_INVALID, "unknown advection form");
       if (value != DNS_ADV_ADVECTIVE && h->quasilinear)
         return fail(h, DNS_E_INVALID, "the quasi-linear dynamics use the advective form");
+      if (!form_fits(h, h->precision, int(value)))
+        return fail(h, DNS_E_UNSUPPORTED, "no advection-kernel variant of this form is built for this grid");
       if (value != h->advection) {
         h->advection = int(value);
         invalidate_graph(h);
@@ -1341,6 +1439,10 @@ int dns_step(dns_handle* h, int nsteps) {
     int rc = refresh_velocities(h);
     if (rc) return rc;
   }
+  if (h->grouped() && grouped_one_launch(h)) {
+    const int rc = update_group_descs(h);
+    if (rc) return rc;
+  }
   if (h->use_graph) {
     if (!h->graph_valid) {
       int rc = build_graph(h);
@@ -1631,7 +1733,7 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
     if (rc) return rc;
   }
   int rows[kMaxPlaneVariants];
-  const int nv = plane_variants(h->precision, plane_form(h), h->Nx, rows);
+  const int nv = plane_variants(h->precision, plane_form(h), h->Nx, h->Nz, rows);
   int best_v = 0;
   double best_p = 1e30;
   for (int v = 0; v < nv; ++v) {

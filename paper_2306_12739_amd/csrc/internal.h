@@ -96,13 +96,13 @@ struct ModeArgs {
 constexpr int kPlaneForms = 4;
 hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, const PlaneArgs& a,
                         hipStream_t s);
-// Plane-kernel variants built for (precision, form, Nx), index 0 being the
+// Plane-kernel variants built for (precision, form, Nx, Nz), index 0 being the
 // default: returns how many (<= kMaxPlaneVariants).  rows[v] is the chunk-row
 // count of variant v, plus kWaveRows for the lane-parallel advective kernel.
 constexpr int kMaxPlaneVariants = 12;
 constexpr int kWaveRows = 100;
 constexpr int kWaveGlobalAcc = 50;
-int plane_variants(int precision, int form, int Nx, int* rows);
+int plane_variants(int precision, int form, int Nx, int Nz, int* rows);
 // Lane-parallel advective kernel (kernels_plane_wave.hip): the kernel of
 // (precision, grid, code) or nullptr, where code is the chunk-row count plus
 // kWaveGlobalAcc for the variant whose forward-z sums live in the output
@@ -112,8 +112,12 @@ int plane_wave_rows(int precision, int Nx, int Nz, int* codes);
 int plane_wave_threads(int Nx, int code);
 bool plane_supported(int Nx, int Nz);
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s);
+// Several ensembles' per-mode kernels in one launch (kernels_mode.hip):
+// descriptor d (device array descs) covers workgroups [first[d], first[d+1]).
+hipError_t launch_mode_grouped(int precision, bool forced, const ModeArgs* descs, const int* first, int ndesc,
+                               int nblk, size_t lds, hipStream_t s);
 // Resolve kernels on the current device before any graph capture uses them.
-hipError_t plane_preload(int Nx);
+hipError_t plane_preload(int Nx, int Nz);
 hipError_t mode_preload();
 hipError_t misc_preload();
 int mode_member_tile(int My, int E);

@@ -36,6 +36,11 @@
 
 #include "internal.h"
 
+// Multiply-adds are fused only within one source expression, so that the same
+// arithmetic inlined into the single-ensemble and the grouped kernel rounds
+// the same way (fusion across statements follows instruction scheduling).
+#pragma clang fp contract(on)
+
 namespace dns {
 
 namespace {
@@ -171,8 +176,10 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 //   S  : solve stack [v0_e; F'_e; v0_o; F'_o] (interior halves), later eta (FH)
 //   S2 : solve stack [eta0_e; G'_e; eta0_o; G'_o], later dv/dy, u, dw/dy (FH)
 //   T  : Q = i kx N_u + i kz N_w (FH), later v (FH), later du/dy (FH)
+// The per-mode work of workgroup `flat` (a group and member tile) of the
+// launch described by `a`.
 template <typename VT, bool kSplit, bool kForce>
-__global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
+__device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int My = a.My, N = a.N, K = a.K, E = a.E, NZ = a.NZ, P = a.P, ET = a.ET;
@@ -187,7 +194,6 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   __shared__ double red[kNT];
   __shared__ double gam_s[64];
 
-  const int flat = xcd_logical_m(blockIdx.x, gridDim.x);
   const int g = flat / a.ntiles;
   const int tile = flat - g * a.ntiles;
   const int nx = g / P, az = g - nx * P;
@@ -725,6 +731,23 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
   }
 }
 
+template <typename VT, bool kSplit, bool kForce>
+__global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
+  mode_body<VT, kSplit, kForce>(a, xcd_logical_m(blockIdx.x, gridDim.x));
+}
+
+// Several ensembles' per-mode work in one launch (uneven grouped ensembles,
+// members of different Re and grid): workgroups [first[d], first[d + 1]) run
+// descriptor d, each with the launch shape it would have alone.
+template <typename VT, bool kSplit, bool kForce>
+__global__ void __launch_bounds__(kNT) mode_grouped_kernel(const ModeArgs* __restrict__ descs,
+                                                           const int* __restrict__ first, int ndesc) {
+  const int b = blockIdx.x;
+  int d = 0;
+  while (d + 1 < ndesc && b >= first[d + 1]) ++d;
+  mode_body<VT, kSplit, kForce>(descs[d], xcd_logical_m(b - first[d], first[d + 1] - first[d]));
+}
+
 // LDS geometry of one workgroup; shared with the host launcher.
 void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR) {
   const int N = My - 2;
@@ -766,10 +789,20 @@ const void* mode_fn(int precision) {
 }
 }  // namespace
 
+namespace {
+template <bool kForce>
+const void* mode_grouped_fn(int precision) {
+  return precision == 0   ? reinterpret_cast<const void*>(&mode_grouped_kernel<double, false, kForce>)
+         : precision == 1 ? reinterpret_cast<const void*>(&mode_grouped_kernel<float, false, kForce>)
+                          : reinterpret_cast<const void*>(&mode_grouped_kernel<float, true, kForce>);
+}
+}  // namespace
+
 // Resolve the per-mode kernel instantiations on the current device.
 hipError_t mode_preload() {
   for (int prec = 0; prec < 3; ++prec) {
-    for (const void* fn : {mode_fn<false>(prec), mode_fn<true>(prec)}) {
+    for (const void* fn : {mode_fn<false>(prec), mode_fn<true>(prec), mode_grouped_fn<false>(prec),
+                           mode_grouped_fn<true>(prec)}) {
       hipFuncAttributes attr;
       const hipError_t err = hipFuncGetAttributes(&attr, fn);
       if (err != hipSuccess) return err;
@@ -788,6 +821,20 @@ hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (err != hipSuccess) return err;
   void* args[] = {const_cast<ModeArgs*>(&a)};
+  err = hipLaunchKernel(fn, dim3(nblk), dim3(kNT), args, lds, s);
+  return err != hipSuccess ? err : hipGetLastError();
+}
+
+// Every descriptor of descs (device, ndesc entries; first: device, ndesc + 1
+// block offsets) in one launch of nblk workgroups with lds bytes of dynamic
+// LDS (the largest of the descriptors'); forced selects the variant that
+// subtracts an external forcing (each descriptor then needs one).
+hipError_t launch_mode_grouped(int precision, bool forced, const ModeArgs* descs, const int* first, int ndesc,
+                               int nblk, size_t lds, hipStream_t s) {
+  const void* fn = forced ? mode_grouped_fn<true>(precision) : mode_grouped_fn<false>(precision);
+  hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (err != hipSuccess) return err;
+  void* args[] = {const_cast<ModeArgs**>(&descs), const_cast<int**>(&first), &ndesc};
   err = hipLaunchKernel(fn, dim3(nblk), dim3(kNT), args, lds, s);
   return err != hipSuccess ? err : hipGetLastError();
 }

@@ -502,17 +502,17 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
 // default, the others are candidates for the tuner.  Every variant keeps the
 // workgroup's LDS within 160 KB.
 namespace {
-constexpr int kVar64[5][3] = {{24, 12, 8}, {16, 24, 8}, {12, 8, 0}, {16, 12, 8}, {18, 12, 0}};
-constexpr int kVar32[5][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 16}, {36, 18, 12}};
+constexpr int kVar64[6][3] = {{24, 12, 8}, {16, 24, 8}, {12, 8, 0}, {16, 12, 8}, {18, 12, 0}, {8, 0, 0}};
+constexpr int kVar32[6][3] = {{24, 12, 8}, {16, 24, 48}, {12, 24, 36}, {32, 24, 16}, {36, 18, 12}, {16, 12, 8}};
 int grid_index(int Nx) {
-  return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : Nx == 72 ? 4 : -1;
+  return Nx == 16 ? 0 : Nx == 32 ? 1 : Nx == 48 ? 2 : Nx == 64 ? 3 : Nx == 72 ? 4 : Nx == 96 ? 5 : -1;
 }
 
 template <typename T, int L, int PP, int Form>
 constexpr bool variant_built() {
-  constexpr int gi = L == 8 ? 0 : L == 16 ? 1 : L == 24 ? 2 : L == 32 ? 3 : L == 36 ? 4 : -1;
-  if constexpr (gi < 0 || (3 * L) % PP != 0) {
-    return false;
+  constexpr int gi = L == 8 ? 0 : L == 16 ? 1 : L == 24 ? 2 : L == 32 ? 3 : L == 36 ? 4 : L == 48 ? 5 : -1;
+  if constexpr (gi < 0 || (3 * L) % PP != 0 || (Form >= 2 && 3 * L > 128)) {
+    return false;  // (the quasi-linear row sums take at most two values per lane)
   } else {
     using Cfg = PlaneCfg<T, L, L, PP>;
     const size_t extra = Form >= 2 ? (3 * Cfg::NPTS + 11 * PP) * sizeof(T) : 0;
@@ -553,6 +553,7 @@ const void* plane_fn_grid(int Nx, int pp) {
     case 48: return plane_fn_rows<T, 24, Form>(pp);
     case 64: return plane_fn_rows<T, 32, Form>(pp);
     case 72: return plane_fn_rows<T, 36, Form>(pp);
+    case 96: return plane_fn_rows<T, 48, Form>(pp);
   }
   return nullptr;
 }
@@ -585,20 +586,23 @@ int table_rows(int precision, int Nx, int* rows) {
 }
 }  // namespace
 
+// Grids with an advective-form variant: the general kernel's square grids,
+// and the lane-parallel kernel's (square or not).
 bool plane_supported(int Nx, int Nz) {
-  return Nx == Nz && (Nx == 16 || Nx == 32 || Nx == 48 || Nx == 64 || Nx == 72);
+  int rows[kMaxPlaneVariants];
+  return plane_variants(1, 0, Nx, Nz, rows) > 0;
 }
 
 // Resolve every built plane-kernel variant of grid Nx (both precisions, every
 // form) on the current device, so that a later graph capture never holds a
 // kernel's first launch.
-hipError_t plane_preload(int Nx) {
+hipError_t plane_preload(int Nx, int Nz) {
   for (int prec = 0; prec < 2; ++prec) {
     for (int form = 0; form < kPlaneForms; ++form) {
       int rows[kMaxPlaneVariants];
-      const int n = plane_variants(prec, form, Nx, rows);  // 0: this form does not fit this grid
+      const int n = plane_variants(prec, form, Nx, Nz, rows);  // 0: this form does not fit this grid
       for (int v = 0; v < n; ++v) {
-        const void* fn = rows[v] > kWaveRows ? plane_wave_fn(prec, Nx, Nx, rows[v] - kWaveRows)
+        const void* fn = rows[v] > kWaveRows ? plane_wave_fn(prec, Nx, Nz, rows[v] - kWaveRows)
                                              : plane_fn(prec, form, Nx, rows[v]);
         if (!fn) return hipErrorInvalidValue;
         hipFuncAttributes attr;
@@ -613,13 +617,14 @@ hipError_t plane_preload(int Nx) {
 // The lane-parallel advective variants first (advective form, grids with a
 // power-of-two Nx/2), then the table's variants that are built for this form
 // (the quasi-linear form needs more LDS and drops the largest chunks).
-int plane_variants(int precision, int form, int Nx, int* rows) {
+int plane_variants(int precision, int form, int Nx, int Nz, int* rows) {
   int n = 0;
   if (form == 0) {
     int wave[6];
-    const int nw = plane_wave_rows(precision, Nx, Nx, wave);
+    const int nw = plane_wave_rows(precision, Nx, Nz, wave);
     for (int v = 0; v < nw; ++v) rows[n++] = kWaveRows + wave[v];
   }
+  if (Nx != Nz) return n;  // the general kernel is built for square grids
   int all[3];
   const int n_all = table_rows(precision, Nx, all);
   for (int v = 0; v < n_all; ++v)
@@ -634,7 +639,7 @@ hipError_t launch_plane(int precision, int form, int Nx, int Nz, int variant, co
                         hipStream_t s) {
   if (!plane_supported(Nx, Nz) || form < 0 || form >= kPlaneForms) return hipErrorInvalidValue;
   int rows[kMaxPlaneVariants];
-  const int n = plane_variants(precision, form, Nx, rows);
+  const int n = plane_variants(precision, form, Nx, Nz, rows);
   if (variant < 0 || variant >= n) return hipErrorInvalidValue;
   const bool wave = rows[variant] > kWaveRows;
   const void* fn = wave ? plane_wave_fn(precision, Nx, Nz, rows[variant] - kWaveRows)

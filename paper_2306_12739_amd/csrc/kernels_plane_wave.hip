@@ -490,40 +490,44 @@ namespace {
 
 // Built (precision, L, chunk rows), default first per grid: the variants whose
 // registers fit without spilling.
-template <typename T, int L, int PP>
+// Built (precision, L = Nx/2, P = Nz/2, chunk rows): on the square grids the
+// variants whose registers fit without spilling; on the non-square grids
+// (Nx, Nz) = (64, 32) and (32, 64) the 16-row chunks.
+template <typename T, int L, int P, int PP>
 constexpr bool wave_built() {
-  if constexpr (sizeof(T) == 4) return (L == 32 && (PP == 32 || PP == 16)) || (L == 16 && (PP == 48 || PP == 16));
+  if constexpr (L != P) return PP == 16 && ((L == 32 && P == 16) || (L == 16 && P == 32));
+  else if constexpr (sizeof(T) == 4) return (L == 32 && (PP == 32 || PP == 16)) || (L == 16 && (PP == 48 || PP == 16));
   else return (L == 32 && PP == 16) || (L == 16 && (PP == 16 || PP == 48));
 }
 
-template <typename T, int L, int PP>
+template <typename T, int L, int P, int PP>
 const void* wave_fn_if_built(bool gacc) {
-  if constexpr (!wave_built<T, L, PP>()) {
+  if constexpr (!wave_built<T, L, P, PP>()) {
     return nullptr;
   } else {
-    using Cfg = WaveCfg<T, L, L, PP>;
+    using Cfg = WaveCfg<T, L, P, PP>;
     static_assert(Cfg::kLdsBytes <= 160 * 1024, "LDS of a built variant");
-    return gacc ? reinterpret_cast<const void*>(&plane_wave_kernel<T, T, L, L, PP, true>)
-                : reinterpret_cast<const void*>(&plane_wave_kernel<T, T, L, L, PP, false>);
+    return gacc ? reinterpret_cast<const void*>(&plane_wave_kernel<T, T, L, P, PP, true>)
+                : reinterpret_cast<const void*>(&plane_wave_kernel<T, T, L, P, PP, false>);
   }
 }
 
-template <typename T, int L>
+template <typename T, int L, int P>
 const void* wave_fn_rows(int pp, bool gacc) {
   switch (pp) {
-    case 16: return wave_fn_if_built<T, L, 16>(gacc);
-    case 32: return wave_fn_if_built<T, L, 32>(gacc);
-    case 48: return wave_fn_if_built<T, L, 48>(gacc);
+    case 16: return wave_fn_if_built<T, L, P, 16>(gacc);
+    case 32: return wave_fn_if_built<T, L, P, 32>(gacc);
+    case 48: return wave_fn_if_built<T, L, P, 48>(gacc);
   }
   return nullptr;
 }
 
 template <typename T>
-const void* wave_fn_t(int Nx, int pp, bool gacc) {
-  switch (Nx) {
-    case 32: return wave_fn_rows<T, 16>(pp, gacc);
-    case 64: return wave_fn_rows<T, 32>(pp, gacc);
-  }
+const void* wave_fn_t(int Nx, int Nz, int pp, bool gacc) {
+  if (Nx == 32 && Nz == 32) return wave_fn_rows<T, 16, 16>(pp, gacc);
+  if (Nx == 64 && Nz == 64) return wave_fn_rows<T, 32, 32>(pp, gacc);
+  if (Nx == 64 && Nz == 32) return wave_fn_rows<T, 32, 16>(pp, gacc);
+  if (Nx == 32 && Nz == 64) return wave_fn_rows<T, 16, 32>(pp, gacc);
   return nullptr;
 }
 
@@ -532,10 +536,9 @@ const void* wave_fn_t(int Nx, int pp, bool gacc) {
 // code: chunk rows, plus kWaveGlobalAcc for the variant that accumulates the
 // forward z transform in the output buffer
 const void* plane_wave_fn(int precision, int Nx, int Nz, int code) {
-  if (Nx != Nz) return nullptr;
   const bool gacc = code >= kWaveGlobalAcc;
   const int pp = code % kWaveGlobalAcc;
-  return precision == 0 ? wave_fn_t<double>(Nx, pp, gacc) : wave_fn_t<float>(Nx, pp, gacc);
+  return precision == 0 ? wave_fn_t<double>(Nx, Nz, pp, gacc) : wave_fn_t<float>(Nx, Nz, pp, gacc);
 }
 
 // Built codes, fastest first as measured on the MI355X (per-launch times of
@@ -549,7 +552,7 @@ int plane_wave_rows(int precision, int Nx, int Nz, int* codes) {
   static constexpr int fp32_64[6] = {32 + G, 16, 16 + G, 32, 48 + G, 48};
   static constexpr int fp64_64[6] = {16 + G, 16, 32 + G, 32, 48 + G, 48};
   static constexpr int other[6] = {16, 16 + G, 48, 48 + G, 32 + G, 32};
-  const int* order = Nx == 64 ? (precision == 0 ? fp64_64 : fp32_64) : other;
+  const int* order = Nx == 64 && Nz == 64 ? (precision == 0 ? fp64_64 : fp32_64) : other;
   int n = 0;
   for (int i = 0; i < 6; ++i)
     if (plane_wave_fn(precision, Nx, Nz, order[i])) codes[n++] = order[i];

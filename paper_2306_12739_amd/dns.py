@@ -38,6 +38,7 @@ OPT_SHARED_MEAN = 9
 OPT_QUASILINEAR = 10
 OPT_FROZEN_MEAN = 11
 OPT_V_DISCRETIZATION = 12
+OPT_GROUP_STREAMS = 13
 
 VDISC_CLAMPED = 0
 VDISC_KMM = 1

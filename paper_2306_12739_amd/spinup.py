@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--applications", type=int, default=8)
     ap.add_argument("--held-out", type=int, default=64)
+    ap.add_argument("--window", type=int, default=100, help="DNS steps per statistics window")
+    ap.add_argument("--windows", type=int, default=20,
+                    help="windows of DNS continuation after the hand-off (20 x 100 = 2000 steps)")
     args = ap.parse_args()
     name = "couette-re600-32x49x32-e64"
     w = inputs.WORKLOADS[name]
@@ -207,11 +210,16 @@ def main():
     del blocks
     torch.cuda.empty_cache()
     held = inputs.workload_state(name, ensemble=args.held_out, seed=3001)
-    d_s, d_0, S, rejected = gain(make, net, held, args.applications, args.gap, 100, 8, check_steps=50)
+    t0 = time.perf_counter()
+    d_s, d_0, S, rejected = gain(make, net, held, args.applications, args.gap, args.window, args.windows,
+                                 check_steps=50)
+    t_gain = time.perf_counter() - t0
     out = {"pairs": npairs, "rounds": rounds, "dns_steps_for_data": rounds * (args.snapshots - 1) * args.gap,
            "data_seconds": t_data, "persistence_loss": persistence, "epoch_loss": hist,
            "train_seconds": t_train, "train_steps": steps, "train_samples_per_s": steps * args.batch / t_train,
            "applications": args.applications, "held_out": args.held_out,
+           "continuation_steps": args.window * args.windows, "window_steps": args.window,
+           "gain_seconds": t_gain,
            "distance_spun_up": d_s, "distance_dns_only": d_0,
            "mean_distance_spun_up": float(np.mean(d_s)), "mean_distance_dns_only": float(np.mean(d_0)),
            "rejected_by_dns": rejected, "failed_members": sum(x["failed"] for x in S),

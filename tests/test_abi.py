@@ -47,6 +47,9 @@ def test_invalid_arguments_fail_before_the_device():
     assert lib.dns_create(ctypes.byref(geo), 400.0, 16, 3, 16, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_INVALID
     assert lib.dns_create(ctypes.byref(geo), 400.0, 16, 33, 16, 0, 0.02, ctypes.byref(h)) == dns.DNS_E_INVALID
     assert lib.dns_create(ctypes.byref(geo), 400.0, 20, 33, 20, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_UNSUPPORTED
+    # non-square grids: only the lane-parallel kernel's pairs are built
+    assert lib.dns_create(ctypes.byref(geo), 400.0, 96, 33, 32, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_UNSUPPORTED
+    assert lib.dns_create(ctypes.byref(geo), 400.0, 48, 33, 16, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_UNSUPPORTED
     assert h.value is None
     assert b"supported" in lib.dns_last_error(None)
     bad = dns.Geometry(7, 1.0, 1.0, 1.0, 0.0)

@@ -1,10 +1,12 @@
 """Grouped (uneven) ensembles: several configurations in one step call (GPU).
 
 The grouped workload holds three Couette groups of different Re and grid
-(16x33x16 / 32x49x32 / 48x65x48; 64 / 40 / 24 members).  Each group's kernels
-are the single-ensemble kernels on a branch of their own, so a grouped run must
-equal, bit for bit, the groups run one at a time; the 48x65x48 grid (not used by
-the other workloads) is also checked against the oracle, on sampled members.
+(16x33x16 / 32x49x32 / 48x65x48; 64 / 40 / 24 members).  By default each
+sub-step runs every group's per-mode work in one launch (a descriptor per
+group); DNS_OPT_GROUP_STREAMS = 1 runs each group's kernels on a stream of its
+own instead.  Either way a grouped run must equal, bit for bit, the groups run
+one at a time; the 48x65x48 grid (not used by the other workloads) is also
+checked against the oracle, on sampled members.
 """
 
 import sys
@@ -40,13 +42,15 @@ GRAPH_SKIP = pytest.mark.skip(
            "host process inside dns_step intermittently, with no cause shown in the library")
 
 
+@pytest.mark.parametrize("streams", [0, 1])
 @pytest.mark.parametrize("graph", [pytest.param(1, marks=GRAPH_SKIP), 0])
 @pytest.mark.parametrize("precision", [dns.PREC_FP64, dns.PREC_MIXED_FP32])
-def test_grouped_equals_groups_run_alone_bitwise(graph, precision):
-    say(f"case: grouped 3 groups, 10 steps, graph={graph} precision={precision} vs alone")
+def test_grouped_equals_groups_run_alone_bitwise(graph, precision, streams):
+    say(f"case: grouped 3 groups, 10 steps, graph={graph} precision={precision} group streams={streams} vs alone")
     states = [inputs.group_state(g) for g in GW["groups"]]
     grp = dns.GroupedEnsemble(GW["groups"])
     grp.set_precision(precision)
+    grp.set_option(dns.OPT_GROUP_STREAMS, streams)
     grp.set_option(dns.OPT_GRAPH, graph)
     for g, st, base in zip(GW["groups"], states, grp.base):
         grp.set_state(*st, member0=int(base))

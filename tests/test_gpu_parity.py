@@ -495,3 +495,44 @@ def test_mixed_precision_error_is_small(precision):
     assert max(e_stage.values()) <= (1e-4 if split else 1e-5)
     assert max(errs[k] for k in ("v", "eta", "U-Ulam", "W")) <= (1e-3 if split else 1e-4)
     gpu.close()
+
+
+def test_parity_channel_96x83x96_fp64():
+    """The 96-mode grid of the paper's C3/P3 cases (95 x 95 x 81 in its count,
+    Table geometry3): 3/2 grid of 144 points, radix 12 x 12 transforms."""
+    say("case: channel 96x83x96 E=2 FP64, 2 steps dt=0.008")
+    st = inputs.random_state(1, 2 * np.pi, np.pi, 96, 83, 96, 2, 0.3, 67, spectrum="k2")
+    gpu, ref = make_pair(1, 3250.0, 2 * np.pi, np.pi, 96, 83, 96, 2, 0.008, st)
+    gpu.step(2)
+    ref.step(2)
+    errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
+    say("errors:", errs)
+    assert_state(errs, 1e-10)
+    gpu.close()
+
+
+@pytest.mark.parametrize("grid", [(64, 49, 32), (32, 49, 64)], ids=lambda g: f"{g[0]}x{g[1]}x{g[2]}")
+def test_parity_nonsquare_grids(grid):
+    """Nx != Nz (the lane-parallel advection kernel; the advective form): FP64
+    against the oracle after 3 steps, and the mixed stage-0 advection terms."""
+    nx, ny, nz = grid
+    say(f"case: channel {nx}x{ny}x{nz} E=2, FP64 3 steps and mixed stage 0")
+    st = inputs.random_state(1, 2 * np.pi, np.pi, nx, ny, nz, 2, 0.3, 71, spectrum="k2")
+    gpu, ref = make_pair(1, 4200.0, 2 * np.pi, np.pi, nx, ny, nz, 2, 0.005, st)
+    rv = ref.velocities(ref.v, ref.eta, ref.U, ref.W)
+    Nu, Nv, Nw, _, _ = ref.nonlinear(rv)
+    for prec, bar in ((dns.PREC_FP64, 1e-12), (dns.PREC_MIXED_FP32, 2e-6)):
+        gpu.set_precision(prec)
+        _, nl, _ = gpu.debug_stage0()
+        errs = [float(np.linalg.norm(nl[i] - f) / np.linalg.norm(f)) for i, f in enumerate((Nu, Nv, Nw))]
+        say(f"  stage-0 advection terms, precision {prec}:", errs)
+        assert max(errs) <= bar
+    gpu.set_precision(dns.PREC_FP64)
+    gpu.step(3)
+    ref.step(3)
+    errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
+    say("errors:", errs)
+    assert_state(errs, 1e-10)
+    with pytest.raises(dns.DnsError):        # only the advective form is built off the square grids
+        gpu.set_advection(dns.ADV_ROTATIONAL)
+    gpu.close()

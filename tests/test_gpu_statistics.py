@@ -127,3 +127,64 @@ def test_mixed_statistics_match_fp64(name):
     for k in ("U", "urms", "vrms", "wrms", "tau_w"):
         assert d_mix[k] <= 0.01, (k, d_mix[k])
         assert d_spl[k] <= 0.01, (k, d_spl[k])
+
+
+DECOR = {"name": "couette-re600-32x49x32-e64", "spinup": 3000, "decorrelate": 6000, "window": 8000}
+
+
+def test_decorrelated_statistics_mixed_vs_fp64():
+    """Mixed precision against FP64 on statistics of trajectories that have
+    decorrelated: both start from one FP64 spun-up turbulent ensemble, run
+    `decorrelate` steps (until the rounding differences have grown to the size
+    of the flow itself), then accumulate over a window of `window` steps.  The
+    difference of each pooled statistic must lie within three combined
+    bootstrap standard errors (members resampled); the record states the
+    window and whether the sampling error resolves the 1 % bar."""
+    d = DECOR
+    w = inputs.WORKLOADS[d["name"]]
+    say(f"case: decorrelated statistics {d['name']}: spin-up {d['spinup']}, "
+        f"decorrelation {d['decorrelate']}, window {d['window']} steps")
+    base = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], w["ensemble"], w["dt"])
+    base.set_precision(dns.PREC_FP64)
+    base.set_option(dns.OPT_GRAPH, 1)
+    base.set_state(*inputs.workload_state(d["name"]))
+    base.step(d["spinup"])
+    s0 = base.get_state()
+    base.close()
+    out, final = {}, {}
+    for prec in (dns.PREC_FP64, dns.PREC_MIXED_FP32):
+        ens = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], w["ensemble"], w["dt"])
+        ens.set_precision(prec)
+        ens.set_option(dns.OPT_GRAPH, 1)
+        ens.set_state(*s0)
+        ens.step(d["decorrelate"])
+        ens.set_option(dns.OPT_STATS, 1)
+        ens.stats_reset()
+        ens.step(d["window"])
+        out[prec] = ens.stats()
+        final[prec] = ens.get_state()
+        ens.close()
+    # the trajectories have separated: member-wise distance of the final v
+    vf, vm = final[dns.PREC_FP64][0], final[dns.PREC_MIXED_FP32][0]
+    sep = float(np.median([np.linalg.norm(vm[i] - vf[i]) / np.linalg.norm(vf[i]) for i in range(vf.shape[0])]))
+    rng = np.random.default_rng(1)
+    flow = w["flow"]
+    f64, mix = out[dns.PREC_FP64], out[dns.PREC_MIXED_FP32]
+    pf = pooled(f64["member_profiles"], f64["member_tau"], flow)
+    pm = pooled(mix["member_profiles"], mix["member_tau"], flow)
+    sef = bootstrap_se(f64["member_profiles"], f64["member_tau"], flow, rng)
+    sem = bootstrap_se(mix["member_profiles"], mix["member_tau"], flow, rng)
+    diff = compare(pm, pf)
+    comb = {k: float(np.hypot(sef[k], sem[k])) for k in sef}
+    rec = {"workload": d["name"], "steps": d, "median_member_separation": sep, "mixed_vs_fp64": diff,
+           "combined_bootstrap_se": comb, "resolves_1pct": bool(max(comb.values()) * 3 <= 0.01),
+           "re_tau_fp64": f64["re_tau"], "re_tau_mixed": mix["re_tau"],
+           "failed": int(f64["failed"].sum() + mix["failed"].sum())}
+    say(json.dumps(rec))
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, f"stats_decorrelated_{d['name']}.json"), "w") as f:
+        json.dump(rec, f)
+    assert rec["failed"] == 0
+    assert sep > 0.1, sep
+    for k in ("U", "urms", "vrms", "wrms", "tau_w"):
+        assert diff[k] <= 3.0 * comb[k], (k, diff[k], comb[k])

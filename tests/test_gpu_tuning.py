@@ -22,15 +22,16 @@ GRIDS = [  # (flow, Re, Lx, Lz, N, Ny, dt, amplitude)
     (0, 1000.0, 1.75 * np.pi, 1.2 * np.pi, 48, 65, 0.02, 0.2),
     (1, 4200.0, 2.0 * np.pi, np.pi, 64, 97, 0.005, 0.3),
     (1, 4200.0, 2.0 * np.pi, np.pi, 72, 73, 0.005, 0.3),
+    (1, 3250.0, 2.0 * np.pi, np.pi, 96, 83, 0.008, 0.3),
 ]
 # built variants, default first: chunk rows of the general kernel, and 100 +
 # chunk rows (+ 50 with the forward-z sums kept in the output buffer) of the
 # lane-parallel advective kernel
 ROWS = {
     dns.PREC_FP64: {16: [24, 12, 8], 32: [116, 166, 148, 198, 16, 24, 8], 48: [12, 8],
-                    64: [166, 116, 16, 12, 8], 72: [12]},
+                    64: [166, 116, 16, 12, 8], 72: [12], 96: [8]},
     dns.PREC_MIXED_FP32: {16: [24, 12, 8], 32: [116, 166, 148, 198, 16, 24, 48], 48: [12, 24, 36],
-                          64: [182, 116, 166, 132, 32, 24, 16], 72: [18, 12]},
+                          64: [182, 116, 166, 132, 32, 24, 16], 72: [18, 12], 96: [16, 12, 8]},
 }
 
 
