@@ -33,6 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # Vector ALU peak: 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.  Packed
 # FP32 instructions are disabled at compile time, so FP32 and FP64 vector peaks are equal.
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# published dense FP64 matrix-core rate of the MI355X
+FP64_MATRIX_TFLOPS = 78.6
 # The published FP32 vector figure counts packed (two-wide) FP32 FMAs.
 FP32_PUBLISHED_TFLOPS = 157.3
 METRIC = "ensemble member-steps/s at Re_tau~180; mixed vs FP64 at <=1% stats error"
@@ -331,7 +333,15 @@ def main():
     for k, t in (("plane", plane_ms), ("mode", mode_ms)):
         b, f = model[k]
         per_kernel[k] = {"ms": t, "GB/s": b / (t * 1e-3) / 1e9, "TFLOP/s": f / (t * 1e-3) / 1e12,
-                         "alg_bytes": b, "alg_flops": f}
+                         "alg_bytes": b, "alg_flops": f,
+                         "traffic": measured_traffic(k, name, args.precision)
+                         if args.advection == "advective" else None}
+    # each kernel against its own roof: the advection kernel is bound by vector-ALU issue
+    # (FFT and product flops against the non-packed vector rate), the per-mode kernel by HBM
+    # (its algorithmic bytes; its FP64 matrix work needs less time at peak)
+    per_kernel["plane"]["frac_valu"] = per_kernel["plane"]["TFLOP/s"] / VALU_PEAK_TFLOPS
+    per_kernel["mode"]["frac_hbm"] = per_kernel["mode"]["GB/s"] / HBM_PEAK_GBS
+    per_kernel["mode"]["frac_fp64_matrix"] = per_kernel["mode"]["TFLOP/s"] / FP64_MATRIX_TFLOPS
     dom = "plane" if plane_ms >= mode_ms else "mode"
     pk = per_kernel[dom]
     if dom == "plane":

@@ -106,6 +106,7 @@ struct dns_handle {
   std::vector<ModeArgs> gdesc_host;
   std::vector<int> gfirst_host;
   size_t glds = 0;
+  std::vector<hipEvent_t> gfork;  // per member chain: start of a sub-step's advection work
   bool grouped() const { return !sub.empty(); }
 };
 
@@ -152,6 +153,9 @@ void free_all(dns_handle* h) {
   for (hipEvent_t e : h->join)
     if (e) hipEventDestroy(e);
   h->join.clear();
+  for (hipEvent_t e : h->gfork)
+    if (e) hipEventDestroy(e);
+  h->gfork.clear();
   for (hipStream_t st : h->chain_stream)
     if (st) hipStreamDestroy(st);
   h->chain_stream.clear();
@@ -488,25 +492,52 @@ bool grouped_one_launch(const dns_handle* h) {
   return true;
 }
 
-// Per-mode descriptors of every group for the three sub-steps (each group's
-// full member range, its own tile shape), uploaded in stream order when they
-// differ from the last upload.
+// Member chains of the grouped one-launch path: two (each group's members
+// split in halves, so that one chain's advection kernels overlap the other's
+// per-mode launch), one when a group shares its streamwise mean across members.
+int grouped_chains(const dns_handle* h) {
+  for (const dns_handle* sh : h->sub)
+    if (sh->shared_mean) return 1;
+  return h->chain_stream.size() >= 2 ? 2 : 1;
+}
+
+// members [e0, e0 + ec) of group g in chain c of nc
+void chain_slice(const dns_handle* sh, int c, int nc, int* e0, int* ec) {
+  const int a = int((long long)sh->E * c / nc), b = int((long long)sh->E * (c + 1) / nc);
+  *e0 = a;
+  *ec = b - a;
+}
+
+// Per-mode descriptors [chain][sub-step][group] (each group's chain slice, its
+// own tile shape) and block offsets [chain][group + 1], uploaded in stream
+// order when they differ from the last upload.
 int update_group_descs(dns_handle* h) {
   const int ng = int(h->sub.size());
-  std::vector<ModeArgs> d(size_t(3) * ng);
-  std::vector<int> first(size_t(ng) + 1, 0);
+  const int nc = grouped_chains(h);
+  std::vector<ModeArgs> d(size_t(nc) * 3 * ng);
+  std::vector<int> first(size_t(nc) * (ng + 1), 0);
   size_t lds = 0;
-  for (int g = 0; g < ng; ++g) {
-    dns_handle* sh = h->sub[g];
-    for (int st = 0; st < 3; ++st) d[size_t(st) * ng + g] = mode_args(sh, st);
-    first[g + 1] = first[g] + sh->G * sh->ntiles;
-    lds = std::max(lds, size_t(2 * sh->SR + sh->TR) * sh->CRP * sizeof(double));
+  for (int c = 0; c < nc; ++c) {
+    int* fc = first.data() + size_t(c) * (ng + 1);
+    for (int g = 0; g < ng; ++g) {
+      dns_handle* sh = h->sub[g];
+      int e0, ec;
+      chain_slice(sh, c, nc, &e0, &ec);
+      for (int st = 0; st < 3; ++st) d[(size_t(c) * 3 + st) * ng + g] = mode_args(sh, st, e0, ec);
+      fc[g + 1] = fc[g] + sh->G * ((ec + sh->ET - 1) / sh->ET);
+      lds = std::max(lds, size_t(2 * sh->SR + sh->TR) * sh->CRP * sizeof(double));
+    }
   }
   const bool same = h->gdesc_host.size() == d.size() &&
                     std::memcmp(h->gdesc_host.data(), d.data(), d.size() * sizeof(ModeArgs)) == 0 &&
                     h->gfirst_host == first;
   if (same) return DNS_OK;
-  if (!h->gdesc) {
+  if (h->gdesc_host.size() != d.size() || h->gfirst_host.size() != first.size()) {
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+    if (h->gdesc) hipFree(h->gdesc);
+    if (h->gfirst) hipFree(h->gfirst);
+    h->gdesc = nullptr;
+    h->gfirst = nullptr;
     HIP_OR_FAIL(h, dalloc(&h->gdesc, d.size()));
     HIP_OR_FAIL(h, dalloc(&h->gfirst, first.size()));
   }
@@ -522,33 +553,63 @@ int update_group_descs(dns_handle* h) {
   return DNS_OK;
 }
 
-// One step of every group with one per-mode launch per sub-step: each group's
-// advection work (and, at the first sub-step, its wall sums and diagnostics)
-// on the group's stream, forked from and joined into h->stream, then one
-// launch of the per-mode kernel over every group's workgroups on h->stream.
+// The stream that runs group sh's advection work for member chain c of the
+// grouped one-launch path: the group's own chain stream, or its main stream.
+hipStream_t group_chain_stream(const dns_handle* sh, int c) {
+  return c < int(sh->chain_stream.size()) ? sh->chain_stream[c] : sh->stream;
+}
+hipEvent_t group_chain_event(const dns_handle* sh, int c) {
+  return c < int(sh->chain_join.size()) ? sh->chain_join[c] : nullptr;
+}
+
+// One step of every group with one per-mode launch per sub-step and member
+// chain.  Each chain runs on a stream of its own forked from and joined into
+// h->stream; in each sub-step it forks again onto every group's stream for
+// that chain, where the group's advection work for the chain's members runs
+// (and, at the first sub-step, their wall sums and diagnostics), joins back
+// and launches the per-mode kernel once over every group's workgroups of
+// those members.
 int enqueue_grouped_one_launch(dns_handle* h) {
   const int ng = int(h->sub.size());
-  const int nblk = h->gfirst_host[ng];
+  const int nc = int(h->gfirst_host.size()) / (ng + 1);
+  HIP_OR_FAIL(h, hipEventRecord(h->chain_fork, h->stream));
+  for (int c = 0; c < nc; ++c) HIP_OR_FAIL(h, hipStreamWaitEvent(h->chain_stream[c], h->chain_fork, 0));
   for (int st = 0; st < 3; ++st) {
-    HIP_OR_FAIL(h, hipEventRecord(h->fork, h->stream));
-    for (int g = 0; g < ng; ++g) {
-      dns_handle* sh = h->sub[g];
-      hipStream_t gs = sh->stream;
-      HIP_OR_FAIL(h, hipStreamWaitEvent(gs, h->fork, 0));
-      HIP_OR_FAIL(h, plane_launch(sh, st == 0, 0, sh->E, gs, false));
-      if (st == 0)
-        HIP_OR_FAIL(h, launch_wall_sums(sh->precision == DNS_PREC_FP64 ? 0 : 1, sh->vel, sh->psum, sh->means,
-                                        sh->My, sh->E, sh->K, sh->NZ, sh->P, sh->kxs, sh->kzs, 0, sh->E, gs));
-      if (sh->shared_mean)
-        HIP_OR_FAIL(h, launch_member_mean(sh->precision == DNS_PREC_FP64 ? 0 : 1, sh->nl, sh->means, sh->My, sh->E,
-                                          sh->K, sh->NZ, gs));
-      if (st == 0) HIP_OR_FAIL(h, launch_stats(stats_args(sh), sh->stats_on ? 1 : 0, gs));
-      HIP_OR_FAIL(h, hipEventRecord(h->join[g], gs));
-      HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->join[g], 0));
+    for (int c = 0; c < nc; ++c) {
+      hipStream_t cs = h->chain_stream[c];
+      const int* fc = h->gfirst_host.data() + size_t(c) * (ng + 1);
+      HIP_OR_FAIL(h, hipEventRecord(h->gfork[c], cs));
+      for (int g = 0; g < ng; ++g) {
+        dns_handle* sh = h->sub[g];
+        int e0, ec;
+        chain_slice(sh, c, nc, &e0, &ec);
+        if (ec == 0) continue;
+        hipStream_t gs = group_chain_stream(sh, c);
+        hipEvent_t ge = group_chain_event(sh, c);
+        if (ge) HIP_OR_FAIL(h, hipStreamWaitEvent(gs, h->gfork[c], 0));
+        else gs = cs;  // no stream of its own for this chain: run on the chain's
+        HIP_OR_FAIL(h, plane_launch(sh, st == 0, e0, ec, gs, false));
+        if (st == 0)
+          HIP_OR_FAIL(h, launch_wall_sums(sh->precision == DNS_PREC_FP64 ? 0 : 1, sh->vel, sh->psum, sh->means,
+                                          sh->My, sh->E, sh->K, sh->NZ, sh->P, sh->kxs, sh->kzs, e0, ec, gs));
+        if (sh->shared_mean)  // one chain holds every member (grouped_chains)
+          HIP_OR_FAIL(h, launch_member_mean(sh->precision == DNS_PREC_FP64 ? 0 : 1, sh->nl, sh->means, sh->My,
+                                            sh->E, sh->K, sh->NZ, gs));
+        if (st == 0) HIP_OR_FAIL(h, launch_stats(stats_args(sh, e0, ec), sh->stats_on ? 1 : 0, gs));
+        if (ge) {
+          HIP_OR_FAIL(h, hipEventRecord(ge, gs));
+          HIP_OR_FAIL(h, hipStreamWaitEvent(cs, ge, 0));
+        }
+      }
+      // every group has the precision of the grouped handle's options (set on all groups)
+      if (fc[ng] > 0)
+        HIP_OR_FAIL(h, launch_mode_grouped(h->sub[0]->precision, false, h->gdesc + (size_t(c) * 3 + st) * ng,
+                                           h->gfirst + size_t(c) * (ng + 1), ng, fc[ng], h->glds, cs));
     }
-    // every group has the precision of the grouped handle's options (set on all groups)
-    HIP_OR_FAIL(h, launch_mode_grouped(h->sub[0]->precision, false, h->gdesc + size_t(st) * ng, h->gfirst, ng, nblk,
-                                       h->glds, h->stream));
+  }
+  for (int c = 0; c < nc; ++c) {
+    HIP_OR_FAIL(h, hipEventRecord(h->chain_join[c], h->chain_stream[c]));
+    HIP_OR_FAIL(h, hipStreamWaitEvent(h->stream, h->chain_join[c], 0));
   }
   return DNS_OK;
 }
@@ -967,6 +1028,13 @@ int dns_create_grouped(const dns_group* groups, int ngroups, dns_handle** out) {
     return bail(DNS_E_HIP, "hipStreamCreate");
   h->stream = h->own_stream;
   h->E = total;
+  // member chains of the one-launch path (two streams, a fork event each)
+  if (set_chains(h, std::min(2, total)) != DNS_OK) return bail(DNS_E_HIP, "creating chain streams");
+  for (size_t c = 0; c < h->chain_stream.size(); ++c) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return bail(DNS_E_HIP, "hipEventCreate");
+    h->gfork.push_back(ev);
+  }
   *out = h;
   return DNS_OK;
 }
