@@ -96,11 +96,11 @@ struct dns_handle {
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   dns_handle* parent = nullptr;
-  // grouped handle: every group's per-mode work in one launch per sub-step
-  // (descriptors [sub-step][group] and block offsets on the device, their host
-  // copy to detect changes); group_streams = true runs each group's kernels on
-  // its own stream instead
-  bool group_streams = false;
+  // grouped handle: group_streams = true (the default) runs each group's
+  // kernels on its own stream; false runs every group's per-mode work in one
+  // launch per sub-step (descriptors [sub-step][group] and block offsets on the
+  // device, their host copy to detect changes)
+  bool group_streams = true;
   ModeArgs* gdesc = nullptr;
   int* gfirst = nullptr;
   std::vector<ModeArgs> gdesc_host;

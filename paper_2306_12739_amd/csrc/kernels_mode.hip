@@ -90,6 +90,179 @@ __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int
   }
 }
 
+// One job of a multi-job contraction: Y = M X for a tiled M (RT row tiles, KT
+// k-steps) and an LDS operand X.
+struct CJob {
+  const double* Mt;
+  int RT, KT;
+  const double* X;
+};
+
+// U k-steps of one tile (or of two tiles, interleaved) from k-step kt while
+// kt + U <= kend: all U fragment loads are issued before the first product,
+// and every tile's products accumulate in ascending k.
+template <int U>
+__device__ __forceinline__ void tile_steps(const double* a, const double* b, int ldx, d4& acc, int& kt, int kend) {
+  for (; kt + U <= kend; kt += U) {
+    double p[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = a[(kt + u) * 64];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = b[(4 * (kt + u)) * ldx];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(p[u], x[u], acc, 0, 0, 0);
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void tile_pair_steps(const double* a1, const double* b1, d4& acc1, const double* a2,
+                                                const double* b2, d4& acc2, int ldx, int& kt, int kend) {
+  for (; kt + U <= kend; kt += U) {
+    double p[U], q[U], x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      p[u] = a1[(kt + u) * 64];
+      q[u] = a2[(kt + u) * 64];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x[u] = b1[(4 * (kt + u)) * ldx];
+      y[u] = b2[(4 * (kt + u)) * ldx];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(p[u], x[u], acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(q[u], y[u], acc2, 0, 0, 0);
+    }
+  }
+}
+
+// k-steps whose fragment loads a wave keeps in flight per tile
+constexpr int kKUnroll = 8;
+
+template <int U>
+__device__ __forceinline__ void tile_tail(const double* a, const double* b, int ldx, d4& acc, int& kt, int kend) {
+  tile_steps<U>(a, b, ldx, acc, kt, kend);
+  if constexpr (U > 1) tile_tail<U / 2>(a, b, ldx, acc, kt, kend);
+}
+
+template <int U>
+__device__ __forceinline__ void tile_pair_tail(const double* a1, const double* b1, d4& acc1, const double* a2,
+                                               const double* b2, d4& acc2, int ldx, int& kt, int kend) {
+  tile_pair_steps<U>(a1, b1, acc1, a2, b2, acc2, ldx, kt, kend);
+  if constexpr (U > 1) tile_pair_tail<U / 2>(a1, b1, acc1, a2, b2, acc2, ldx, kt, kend);
+}
+
+// Output tiles (rt1, ct1) of J1 and, if has2, (rt2, ct2) of J2, with their
+// fragment loads interleaved so that a wave keeps twice as many loads in
+// flight; each tile's products accumulate in ascending k from zero, as in
+// mfma_contract, so the results equal its results.
+__device__ __forceinline__ void mfma_tile_pair(const CJob J1, int rt1, int ct1, bool has2, const CJob J2, int rt2,
+                                               int ct2, int ldx, d4& acc1, d4& acc2) {
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  const double* a1 = J1.Mt + size_t(rt1) * J1.KT * 64 + lane;
+  const double* b1 = J1.X + lk * ldx + ct1 * 16 + lr;
+  acc1 = d4{0.0, 0.0, 0.0, 0.0};
+  acc2 = d4{0.0, 0.0, 0.0, 0.0};
+  int kt = 0;
+  if (has2) {
+    const double* a2 = J2.Mt + size_t(rt2) * J2.KT * 64 + lane;
+    const double* b2 = J2.X + lk * ldx + ct2 * 16 + lr;
+    const int kc = J1.KT < J2.KT ? J1.KT : J2.KT;
+    tile_pair_tail<kKUnroll>(a1, b1, acc1, a2, b2, acc2, ldx, kt, kc);
+    int k2 = kt;
+    tile_tail<kKUnroll>(a2, b2, ldx, acc2, k2, J2.KT);
+  }
+  tile_tail<kKUnroll>(a1, b1, ldx, acc1, kt, J1.KT);
+}
+
+// Every output tile of NJ jobs that share the column tiling (CT) and the
+// operand row stride ldx: tiles are numbered job-major and wave w takes tiles
+// w, w + kWaves, ... two at a time.  store(job, row, col, value) as in
+// mfma_contract.  kDefer: every wave first computes all its tiles (at most
+// kMaxHeld) into registers, the workgroup synchronises, then the stores run,
+// so a job may overwrite any job's operand; the caller checks the tile count
+// (mfma_jobs_fit).
+constexpr int kMaxHeld = 4;
+template <int NJ>
+__device__ __forceinline__ bool mfma_jobs_fit(const CJob (&job)[NJ], int CT) {
+  int total = 0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) total += job[j].RT * CT;
+  return total <= kMaxHeld * kWaves;
+}
+
+template <bool kDefer, int NJ, class Store>
+__device__ __forceinline__ void mfma_jobs(const CJob (&job)[NJ], int ldx, int CT, Store store) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  int base[NJ + 1];
+  base[0] = 0;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) base[j + 1] = base[j] + job[j].RT * CT;
+  const int total = base[NJ];
+  // tile t -> job, row tile, column tile; t is uniform over the wave, so the
+  // job is chosen by selects rather than by indexing (no stack copy)
+  auto decode = [&](int t, CJob* J, int* j, int* rt, int* ct) {
+    int jj = 0, b0 = 0;
+    CJob sel = job[0];
+#pragma unroll
+    for (int q = 1; q < NJ; ++q) {
+      if (t >= base[q]) {
+        jj = q;
+        b0 = base[q];
+        sel = job[q];
+      }
+    }
+    const int local = t - b0;
+    *J = sel;
+    *j = jj;
+    *rt = local / CT;
+    *ct = local - *rt * CT;
+  };
+  auto put = [&](int t, const d4& acc) {
+    CJob J;
+    int j, rt, ct;
+    decode(t, &J, &j, &rt, &ct);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(j, rt * 16 + lk + 4 * r, ct * 16 + lr, acc[r]);
+  };
+  if constexpr (kDefer) {
+    d4 held[kMaxHeld];
+#pragma unroll
+    for (int i = 0; i < kMaxHeld; i += 2) {
+      const int t1 = wave + i * kWaves, t2 = t1 + kWaves;
+      if (t1 < total) {
+        CJob J1, J2 = job[0];
+        int j1, rt1, ct1, j2 = 0, rt2 = 0, ct2 = 0;
+        decode(t1, &J1, &j1, &rt1, &ct1);
+        if (t2 < total) decode(t2, &J2, &j2, &rt2, &ct2);
+        mfma_tile_pair(J1, rt1, ct1, t2 < total, J2, rt2, ct2, ldx, held[i], held[i + 1]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxHeld; ++i) {
+      const int t = wave + i * kWaves;
+      if (t < total) put(t, held[i]);
+    }
+  } else {
+    for (int t1 = wave; t1 < total; t1 += 2 * kWaves) {
+      const int t2 = t1 + kWaves;
+      CJob J1, J2 = job[0];
+      int j1, rt1, ct1, j2 = 0, rt2 = 0, ct2 = 0;
+      decode(t1, &J1, &j1, &rt1, &ct1);
+      if (t2 < total) decode(t2, &J2, &j2, &rt2, &ct2);
+      d4 acc1, acc2;
+      mfma_tile_pair(J1, rt1, ct1, t2 < total, J2, rt2, ct2, ldx, acc1, acc2);
+      put(t1, acc1);
+      if (t2 < total) put(t2, acc2);
+    }
+  }
+}
+
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -250,23 +423,34 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   if (!mean_group) {
     // ===================== fluctuation modes (k^2 > 0) =====================
     if (s >= 0) {
-      // Q on every node (FH), -k^2 N_v and G on interior nodes (solve stacks)
-      for (int q = tid; q < Fe * C; q += kNT) {
+      // Q on every node (FH), -k^2 N_v and G on interior nodes (solve stacks).
+      // Both nodes are loaded unconditionally (at the centre node of an odd
+      // grid they coincide, giving he = x, ho = 0), one complex value per
+      // load; a thread issues the loads of two items before either's stores
+      // (an item outside the tile loads element 0 and stores nothing).
+      typedef typename Pair<VT>::type P2;
+      auto nl_load = [&](int q, P2 (&x1)[3], P2 (&x2)[3]) {
         const int k = q >> cs, c = q & (C - 1);
-        if (!col_valid(c)) continue;
+        const bool ok = q < Fe * C && col_valid(c);
+        const size_t o1 = ok ? sb(k, c) : 0, o2 = ok ? sb(My - 1 - k, c) : 0;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          x1[f] = *reinterpret_cast<const P2*>(nl + f * FS + o1);
+          x2[f] = *reinterpret_cast<const P2*>(nl + f * FS + o2);
+        }
+        return ok;
+      };
+      auto nl_item = [&](int q, const P2 (&x1)[3], const P2 (&x2)[3]) {
+        const int k = q >> cs, c = q & (C - 1);
         const double kz = col_kz(c), k2 = kx * kx + kz * kz;
         const bool pair = k < Fo;
-        const size_t o1 = sb(k, c), o2 = sb(My - 1 - k, c);
         double he[6], ho[6];
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-#pragma unroll
-          for (int ri = 0; ri < 2; ++ri) {
-            const double x1 = nl[f * FS + o1 + ri];
-            const double x2 = pair ? double(nl[f * FS + o2 + ri]) : x1;
-            he[2 * f + ri] = 0.5 * (x1 + x2);
-            ho[2 * f + ri] = 0.5 * (x1 - x2);
-          }
+          he[2 * f] = 0.5 * (double(x1[f].x) + double(x2[f].x));
+          ho[2 * f] = 0.5 * (double(x1[f].x) - double(x2[f].x));
+          he[2 * f + 1] = 0.5 * (double(x1[f].y) + double(x2[f].y));
+          ho[2 * f + 1] = 0.5 * (double(x1[f].y) - double(x2[f].y));
         }
         // Q = i kx N_u + i kz N_w
         T[k * CRP + 2 * c] = -(kx * he[1] + kz * he[5]);
@@ -288,105 +472,168 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
             S2[(2 * He + Ho + kk) * CRP + 2 * c + 1] = kz * ho[0] - kx * ho[4];
           }
         }
+      };
+      for (int q = tid; q < Fe * C; q += 2 * kNT) {
+        P2 a1[3], a2[3], b1[3], b2[3];
+        const bool oka = nl_load(q, a1, a2);
+        const bool okb = nl_load(q + kNT, b1, b2);
+        if (oka) nl_item(q, a1, a2);
+        if (okb) nl_item(q + kNT, b1, b2);
       }
       __syncthreads();
       // F = -k^2 N_v - D1 Q: odd F from even Q, even F from odd Q
-      dcontract<kSplit>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
-        if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
-      });
-      dcontract<kSplit>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
-        if (r < He) S[(He + r) * CRP + cc] -= v;
-      });
+      if constexpr (kSplit) {
+        dcontract<kSplit>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+          if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
+        });
+        dcontract<kSplit>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+          if (r < He) S[(He + r) * CRP + cc] -= v;
+        });
+      } else {
+        const CJob jf[2] = {{a.D1intT_e, RTo, (Fe + 3) / 4, T}, {a.D1intT_o, RTe, (Fo + 3) / 4, T + size_t(Fe) * CRP}};
+        mfma_jobs<false>(jf, CRP, CT, [&](int j, int r, int cc, double v) {
+          if (j == 0) {
+            if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
+          } else if (r < He) {
+            S[(He + r) * CRP + cc] -= v;
+          }
+        });
+      }
       __syncthreads();
-      // RK3 combination on halves (history kept in half layout); v0, eta0 halves
-      for (int q = tid; q < N * C; q += kNT) {
+      // RK3 combination on halves (history kept in half layout); v0, eta0
+      // halves.  Half of interior nodes kk and N-1-kk: 0.5 (x1 + sg x2); at the
+      // centre node of an odd N the two nodes coincide (sg = 1) and this is
+      // x1 exactly, so every load is unconditional; two items per thread.
+      // (an item outside the tile loads element 0 and stores nothing)
+      struct RkIn {
+        double2 v1, v2, e1, e2, hf, hg;
+        bool ok;
+      };
+      auto rk_offsets = [&](int q, size_t* s1, size_t* s2, size_t* so) {
         const int hr = q >> cs, c = q & (C - 1);
-        if (!col_valid(c)) continue;
+        const bool ok = q < N * C && col_valid(c);
+        const int kk = hr < He ? hr : hr - He;
+        *s1 = ok ? st(kk, c) : 0;
+        *s2 = ok ? st(N - 1 - kk, c) : 0;
+        *so = ok ? st(hr, c) : 0;
+        return ok;
+      };
+      auto rk_load = [&](int q, RkIn& in) {
+        size_t s1, s2, so;
+        in.ok = rk_offsets(q, &s1, &s2, &so);
+        in.v1 = *reinterpret_cast<const double2*>(a.v + s1);
+        in.v2 = *reinterpret_cast<const double2*>(a.v + s2);
+        in.e1 = *reinterpret_cast<const double2*>(a.eta + s1);
+        in.e2 = *reinterpret_cast<const double2*>(a.eta + s2);
+      };
+      auto rk_load_hist = [&](int q, RkIn& in) {
+        size_t s1, s2, so;
+        rk_offsets(q, &s1, &s2, &so);
+        in.hf = *reinterpret_cast<const double2*>(a.hF + so);
+        in.hg = *reinterpret_cast<const double2*>(a.hG + so);
+      };
+      auto rk_item = [&](int q, const RkIn& in) {
+        const int hr = q >> cs, c = q & (C - 1);
         const bool even = hr < He;
         const int kk = even ? hr : hr - He;
         const int rowF = even ? He + kk : 2 * He + Ho + kk;
         const int rowX = even ? kk : 2 * He + kk;
+        const size_t s1 = st(kk, c), s2 = st(N - 1 - kk, c);
+        const double sg = even ? 1.0 : -1.0;
+        const double2 v1 = in.v1, v2 = in.v2, e1 = in.e1, e2 = in.e2, Hf = in.hf, Hg = in.hg;
+        const size_t so = st(hr, c);
+        double2* hf = reinterpret_cast<double2*>(a.hF + so);
+        double2* hg = reinterpret_cast<double2*>(a.hG + so);
         double Fr = S[rowF * CRP + 2 * c], Fi = S[rowF * CRP + 2 * c + 1];
         double Gr = S2[rowF * CRP + 2 * c], Gi = S2[rowF * CRP + 2 * c + 1];
         if constexpr (kForce) {
           // external forcing held over the step enters every sub-step's terms
           // as F - f_lapv, G - f_eta (y-parity halves of the interior values)
-          const size_t f1 = st(kk, c), f2 = st(N - 1 - kk, c);
-          const double sgn = even ? 1.0 : -1.0;
-          if (even && kk == Ho) {
-            Fr -= a.fv[f1];
-            Fi -= a.fv[f1 + 1];
-            Gr -= a.feta[f1];
-            Gi -= a.feta[f1 + 1];
-          } else {
-            Fr -= 0.5 * (a.fv[f1] + sgn * a.fv[f2]);
-            Fi -= 0.5 * (a.fv[f1 + 1] + sgn * a.fv[f2 + 1]);
-            Gr -= 0.5 * (a.feta[f1] + sgn * a.feta[f2]);
-            Gi -= 0.5 * (a.feta[f1 + 1] + sgn * a.feta[f2 + 1]);
-          }
+          const double2 p1 = *reinterpret_cast<const double2*>(a.fv + s1);
+          const double2 p2 = *reinterpret_cast<const double2*>(a.fv + s2);
+          const double2 g1 = *reinterpret_cast<const double2*>(a.feta + s1);
+          const double2 g2 = *reinterpret_cast<const double2*>(a.feta + s2);
+          Fr -= 0.5 * (p1.x + sg * p2.x);
+          Fi -= 0.5 * (p1.y + sg * p2.y);
+          Gr -= 0.5 * (g1.x + sg * g2.x);
+          Gi -= 0.5 * (g1.y + sg * g2.y);
         }
-        const size_t so = st(hr, c);
-        double* hf = a.hF + so;
-        double* hg = a.hG + so;
         if (s == 0) {
-          hf[0] = Fr; hf[1] = Fi;
-          hg[0] = Gr; hg[1] = Gi;
+          *hf = double2{Fr, Fi};
+          *hg = double2{Gr, Gi};
         } else if (s == 1) {
-          const double Hr = hf[0], Hi = hf[1], HGr = hg[0], HGi = hg[1];
-          hf[0] = Hr + 4.0 * Fr; hf[1] = Hi + 4.0 * Fi;
-          hg[0] = HGr + 4.0 * Gr; hg[1] = HGi + 4.0 * Gi;
-          Fr = 2.0 * Fr - Hr; Fi = 2.0 * Fi - Hi;
-          Gr = 2.0 * Gr - HGr; Gi = 2.0 * Gi - HGi;
+          *hf = double2{Hf.x + 4.0 * Fr, Hf.y + 4.0 * Fi};
+          *hg = double2{Hg.x + 4.0 * Gr, Hg.y + 4.0 * Gi};
+          Fr = 2.0 * Fr - Hf.x; Fi = 2.0 * Fi - Hf.y;
+          Gr = 2.0 * Gr - Hg.x; Gi = 2.0 * Gi - Hg.y;
         } else {
-          Fr = (hf[0] + Fr) * (1.0 / 6.0); Fi = (hf[1] + Fi) * (1.0 / 6.0);
-          Gr = (hg[0] + Gr) * (1.0 / 6.0); Gi = (hg[1] + Gi) * (1.0 / 6.0);
+          Fr = (Hf.x + Fr) * (1.0 / 6.0); Fi = (Hf.y + Fi) * (1.0 / 6.0);
+          Gr = (Hg.x + Gr) * (1.0 / 6.0); Gi = (Hg.y + Gi) * (1.0 / 6.0);
         }
         S[rowF * CRP + 2 * c] = -hdt * Fr;
         S[rowF * CRP + 2 * c + 1] = -hdt * Fi;
         S2[rowF * CRP + 2 * c] = -hdt * Gr;
         S2[rowF * CRP + 2 * c + 1] = -hdt * Gi;
-        // state halves from interior nodes kk and N-1-kk
-        const size_t s1 = st(kk, c), s2 = st(N - 1 - kk, c);
-        const double sg = even ? 1.0 : -1.0;
-        const bool center = even && kk == Ho;  // only when N is odd
-        const double vr = center ? a.v[s1] : 0.5 * (a.v[s1] + sg * a.v[s2]);
-        const double vi = center ? a.v[s1 + 1] : 0.5 * (a.v[s1 + 1] + sg * a.v[s2 + 1]);
-        const double er = center ? a.eta[s1] : 0.5 * (a.eta[s1] + sg * a.eta[s2]);
-        const double ei = center ? a.eta[s1 + 1] : 0.5 * (a.eta[s1 + 1] + sg * a.eta[s2 + 1]);
-        S[rowX * CRP + 2 * c] = vr;
-        S[rowX * CRP + 2 * c + 1] = vi;
-        S2[rowX * CRP + 2 * c] = er;
-        S2[rowX * CRP + 2 * c + 1] = ei;
+        S[rowX * CRP + 2 * c] = 0.5 * (v1.x + sg * v2.x);
+        S[rowX * CRP + 2 * c + 1] = 0.5 * (v1.y + sg * v2.y);
+        S2[rowX * CRP + 2 * c] = 0.5 * (e1.x + sg * e2.x);
+        S2[rowX * CRP + 2 * c + 1] = 0.5 * (e1.y + sg * e2.y);
+      };
+      for (int q = tid; q < N * C; q += 2 * kNT) {
+        RkIn ia, ib;
+        rk_load(q, ia);
+        rk_load(q + kNT, ib);
+        ia.hf = ib.hf = ia.hg = ib.hg = double2{0.0, 0.0};
+        if (s > 0) {
+          rk_load_hist(q, ia);
+          rk_load_hist(q + kNT, ib);
+        }
+        if (ia.ok) rk_item(q, ia);
+        if (ib.ok) rk_item(q + kNT, ib);
       }
       __syncthreads();
       const double* opve = a.opsT + size_t(g) * a.op_group_stride;
       const double* opvo = opve + size_t(RTe) * KSe * 64;
       const double* opee = opvo + size_t(RTo) * KSo * 64;
       const double* opeo = opee + size_t(RTe) * KSe * 64;
-      // v halves -> T (FH, interior rows from 1); the wall rows read as v = 0
+      // v halves -> T (FH, interior rows from 1); the wall rows read as v = 0.
+      // eta halves -> S (FH); rows beyond My keep finite stack data that only
+      // meets zero padding columns of D1.  Both solves in one pass when every
+      // wave can hold its tiles until the v stack in S has been read.
       for (int q = tid; q < CRP; q += kNT) {
         T[q] = 0.0;
         T[Fe * CRP + q] = 0.0;
       }
-      mfma_contract(opve, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
-        if (r < He) T[(1 + r) * CRP + cc] = v;
-      });
-      mfma_contract(opvo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
-        if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
-      });
-      __syncthreads();
-      // eta halves -> S (FH); rows beyond My keep finite stack data that only
-      // meets zero padding columns of D1
-      for (int q = tid; q < CRP; q += kNT) {
-        S[q] = 0.0;
-        S[Fe * CRP + q] = 0.0;
+      const CJob js[4] = {{opve, RTe, KSe, S}, {opvo, RTo, KSo, S + size_t(2 * He) * CRP},
+                          {opee, RTe, KSe, S2}, {opeo, RTo, KSo, S2 + size_t(2 * He) * CRP}};
+      if (mfma_jobs_fit(js, CT)) {
+        mfma_jobs<true>(js, CRP, CT, [&](int j, int r, int cc, double v) {
+          const int lim = (j & 1) ? Ho : He;
+          if (r < lim) ((j < 2) ? T : S)[((j & 1) ? Fe + 1 + r : 1 + r) * CRP + cc] = v;
+        });
+        for (int q = tid; q < CRP; q += kNT) {
+          S[q] = 0.0;
+          S[Fe * CRP + q] = 0.0;
+        }
+      } else {
+        mfma_contract(opve, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+          if (r < He) T[(1 + r) * CRP + cc] = v;
+        });
+        mfma_contract(opvo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+          if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
+        });
+        __syncthreads();
+        for (int q = tid; q < CRP; q += kNT) {
+          S[q] = 0.0;
+          S[Fe * CRP + q] = 0.0;
+        }
+        mfma_contract(opee, RTe, KSe, S2, CRP, CT, [&](int r, int cc, double v) {
+          if (r < He) S[(1 + r) * CRP + cc] = v;
+        });
+        mfma_contract(opeo, RTo, KSo, S2 + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+          if (r < Ho) S[(Fe + 1 + r) * CRP + cc] = v;
+        });
       }
-      mfma_contract(opee, RTe, KSe, S2, CRP, CT, [&](int r, int cc, double v) {
-        if (r < He) S[(1 + r) * CRP + cc] = v;
-      });
-      mfma_contract(opeo, RTo, KSo, S2 + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
-        if (r < Ho) S[(Fe + 1 + r) * CRP + cc] = v;
-      });
       __syncthreads();
       if (s == 2) {
         // Hermitian projection of the n_x = 0 column: (0, nz) and (0, -nz);
@@ -469,12 +716,23 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     }
     __syncthreads();
     // ---- velocity recovery: dv/dy = D1c v (odd <- even, even <- odd) -> S2 FH
-    dcontract<kSplit>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
-      if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
-    });
-    dcontract<kSplit>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
-      if (r < Fe) S2[r * CRP + cc] = v;
-    });
+    if constexpr (kSplit) {
+      dcontract<kSplit>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
+      });
+      dcontract<kSplit>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Fe) S2[r * CRP + cc] = v;
+      });
+    } else {
+      const CJob jc[2] = {{a.D1cT_e, RFo, (He + 3) / 4, T + CRP}, {a.D1cT_o, RFe, (Ho + 3) / 4, T + size_t(Fe + 1) * CRP}};
+      mfma_jobs<false>(jc, CRP, CT, [&](int j, int r, int cc, double v) {
+        if (j == 0) {
+          if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
+        } else if (r < Fe) {
+          S2[r * CRP + cc] = v;
+        }
+      });
+    }
     __syncthreads();
     double dmax = 0.0;
     for (int q = tid; q < Fe * C; q += kNT) {
@@ -518,20 +776,35 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
     }
     __syncthreads();
-    // du/dy = D1 u -> T (FH); then dw/dy = D1 w -> S2 (FH)
-    dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
-      if (r < Fo) T[(Fe + r) * CRP + cc] = v;
-    });
-    dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
-      if (r < Fe) T[r * CRP + cc] = v;
-    });
-    __syncthreads();
-    dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
-      if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
-    });
-    dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
-      if (r < Fe) S2[r * CRP + cc] = v;
-    });
+    // du/dy = D1 u -> T (FH) and dw/dy = D1 w -> S2 (FH): in one pass when
+    // every wave can hold its tiles until u in S2 has been read
+    const CJob jd[4] = {{a.D1T_e, RFo, (Fe + 3) / 4, S2}, {a.D1T_o, RFe, (Fo + 3) / 4, S2 + size_t(Fe) * CRP},
+                        {a.D1T_e, RFo, (Fe + 3) / 4, S}, {a.D1T_o, RFe, (Fo + 3) / 4, S + size_t(Fe) * CRP}};
+    bool merged = false;
+    if constexpr (!kSplit) {
+      if (mfma_jobs_fit(jd, CT)) {
+        mfma_jobs<true>(jd, CRP, CT, [&](int j, int r, int cc, double v) {
+          const int lim = (j & 1) ? Fe : Fo;
+          if (r < lim) ((j < 2) ? T : S2)[((j & 1) ? r : Fe + r) * CRP + cc] = v;
+        });
+        merged = true;
+      }
+    }
+    if (!merged) {
+      dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Fo) T[(Fe + r) * CRP + cc] = v;
+      });
+      dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Fe) T[r * CRP + cc] = v;
+      });
+      __syncthreads();
+      dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
+      });
+      dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        if (r < Fe) S2[r * CRP + cc] = v;
+      });
+    }
     __syncthreads();
     for (int q = tid; q < Fe * C; q += kNT) {
       const int k = q >> cs, c = q & (C - 1);

@@ -129,6 +129,14 @@ def library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2306_12739_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one;
+    # loading torch first makes the library bind to that one, so a process
+    # holds a single runtime (with the library loaded first, torch later finds
+    # no device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.dns_create.argtypes = [ctypes.POINTER(Geometry), ctypes.c_double, ctypes.c_int, ctypes.c_int,
