@@ -64,7 +64,7 @@ typedef struct {
  *   Nx, Nz : 16, 32, 48, 64, 72 or 96 with Nx == Nz, or (Nx, Nz) = (64, 32)
  *            or (32, 64) (advective form only: DNS_OPT_ADVECTION and
  *            DNS_OPT_QUASILINEAR then return DNS_E_UNSUPPORTED);
- *            Ny : 5..252 (odd or even);
+ *            Ny : 5..254 (odd or even);
  *   ensemble >= 1; dt > 0; Re > 0.
  * The state is initialised to the laminar profile (Couette U = Uw y, channel
  * U = 1 - y^2) with zero perturbations.  Device memory is owned by the handle.

@@ -133,9 +133,6 @@ hipError_t dalloc(T** p, size_t count) {
   return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
 }
 
-// static LDS of the per-mode kernel (reduction scratch and per-member gamma)
-constexpr size_t kModeStaticLds = 2560;
-
 size_t vt_size(int precision) { return precision == DNS_PREC_FP64 ? sizeof(double) : sizeof(float); }
 
 void destroy_one(dns_handle* h);
@@ -360,7 +357,7 @@ bool mode_tile_ok(const dns_handle* h, int et) {
   if (et > 1 && et / 2 >= h->E) return false;
   int crp, sr, tr;
   mode_lds_geometry(h->My, et, &crp, &sr, &tr);
-  return size_t(2 * sr + tr) * crp * sizeof(double) <= 160 * 1024;
+  return size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds <= kLdsPerCU;
 }
 
 void set_mode_tile(dns_handle* h, int et) {
@@ -783,11 +780,11 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
                 "grid not built: Nx == Nz in {16, 32, 48, 64, 72, 96}, and (Nx, Nz) = (64, 32) or (32, 64) "
                 "for the advective form, are supported");
   {
-    // one member per per-mode workgroup must fit the workgroup LDS (Ny <= 252)
+    // one member per per-mode workgroup must fit the workgroup LDS (Ny <= 254)
     int crp, sr, tr;
     mode_lds_geometry(Ny, 1, &crp, &sr, &tr);
-    if (size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds > 160 * 1024)
-      return fail(nullptr, DNS_E_UNSUPPORTED, "Ny too large: the per-mode kernel's LDS holds Ny <= 252");
+    if (size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds > kLdsPerCU)
+      return fail(nullptr, DNS_E_UNSUPPORTED, "Ny too large: the per-mode kernel's LDS holds Ny <= 254");
   }
 
   dns_handle* h = new dns_handle();

@@ -122,6 +122,11 @@ hipError_t mode_preload();
 hipError_t misc_preload();
 int mode_member_tile(int My, int E);
 void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR);
+// per-mode workgroup: threads, and its static LDS (per-wave reduction slots of
+// up to 16 columns, per-member gamma); LDS of one CU
+constexpr int kModeThreads = 512;
+constexpr size_t kModeStaticLds = (kModeThreads / 64 * 16 + 64) * sizeof(double);
+constexpr size_t kLdsPerCU = 160 * 1024;
 
 // Row-major R x Kd matrix -> bfloat16 A-operand tiles of the 16x16x16 BF16 MFMA,
 // split M = hi + lo (each rounded to nearest even): tile (rt, kt), kt <

@@ -51,8 +51,9 @@ __device__ __forceinline__ int xcd_logical_m(int b, int nblk) {
   return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
 }
 
-constexpr int kNT = 256;
+constexpr int kNT = kModeThreads;
 constexpr int kWaves = kNT / 64;
+static_assert(kModeStaticLds == (kWaves * 16 + 64) * sizeof(double), "static LDS of mode_body");
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -364,7 +365,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   double* S = smem;
   double* S2 = S + size_t(SR) * CRP;
   double* T = S2 + size_t(SR) * CRP;
-  __shared__ double red[kNT];
+  __shared__ double red[kWaves * 16];  // per-wave maxima of <= 16 columns
   __shared__ double gam_s[64];
 
   const int g = flat / a.ntiles;
@@ -813,12 +814,15 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       write_pair(S2, k, c, 4);
     }
     if (s == 2 || s < 0) {
-      red[tid] = dmax;
+      // thread tid's maximum belongs to column tid mod C: lanes that differ
+      // in bits >= log2 C share it; then one value per wave and column
+      for (int off = C; off < 64; off <<= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+      const int lane = tid & 63, wave = tid >> 6;
+      if (lane < C) red[wave * C + lane] = dmax;
       __syncthreads();
       if (tid < C && col_valid(tid)) {
         double mx = 0.0;
-        for (int q = 0; q < kNT; ++q)
-          if ((q & (C - 1)) == tid) mx = fmax(mx, red[q]);
+        for (int w = 0; w < kWaves; ++w) mx = fmax(mx, red[w * C + tid]);
         atomicMax(&a.divmax[col_member(tid)], (unsigned long long)__double_as_longlong(mx));
       }
     }
@@ -1004,8 +1008,10 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   }
 }
 
+// Four waves per SIMD (registers <= 128): two workgroups of eight waves per CU
+// when their LDS allows.
 template <typename VT, bool kSplit, bool kForce>
-__global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) mode_kernel(ModeArgs a) {
   mode_body<VT, kSplit, kForce>(a, xcd_logical_m(blockIdx.x, gridDim.x));
 }
 
@@ -1013,7 +1019,7 @@ __global__ void __launch_bounds__(kNT) mode_kernel(ModeArgs a) {
 // members of different Re and grid): workgroups [first[d], first[d + 1]) run
 // descriptor d, each with the launch shape it would have alone.
 template <typename VT, bool kSplit, bool kForce>
-__global__ void __launch_bounds__(kNT) mode_grouped_kernel(const ModeArgs* __restrict__ descs,
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) mode_grouped_kernel(const ModeArgs* __restrict__ descs,
                                                            const int* __restrict__ first, int ndesc) {
   const int b = blockIdx.x;
   int d = 0;
@@ -1047,8 +1053,8 @@ int mode_member_tile(int My, int E) {
   for (int et = 1; et <= 8 && et <= E; et *= 2) {
     int crp, sr, tr;
     mode_lds_geometry(My, et, &crp, &sr, &tr);
-    const size_t lds = size_t(2 * sr + tr) * crp * sizeof(double);
-    if (lds <= 78 * 1024) best = et;
+    const size_t lds = size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds;
+    if (2 * lds <= kLdsPerCU) best = et;
   }
   return best;
 }

@@ -109,7 +109,7 @@ def test_ny_beyond_mode_lds_is_unsupported_without_gpu():
     lib = dns.library()
     h = ctypes.c_void_p()
     geo = dns.Geometry(0, 1.75 * np.pi, 1.2 * np.pi, 1.0, 0.0)
-    assert lib.dns_create(ctypes.byref(geo), 400.0, 16, 253, 16, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_UNSUPPORTED
+    assert lib.dns_create(ctypes.byref(geo), 400.0, 16, 255, 16, 2, 0.02, ctypes.byref(h)) == dns.DNS_E_UNSUPPORTED
     assert b"Ny" in lib.dns_last_error(None)
 
 

@@ -119,12 +119,12 @@ def test_parity_edge_grids_fp64(case):
 
 
 def test_largest_ny_runs_at_the_lds_limit():
-    say("case: Couette 16x252x16 (largest Ny), laminar fixed point and a perturbed member, FP64")
+    say("case: Couette 16x254x16 (largest Ny), laminar fixed point and a perturbed member, FP64")
     Lx, Lz = 1.75 * np.pi, 1.2 * np.pi
-    gpu = dns.Ensemble(0, 400.0, Lx, Lz, 16, 252, 16, 2, 0.005)
+    gpu = dns.Ensemble(0, 400.0, Lx, Lz, 16, 254, 16, 2, 0.005)
     v, eta, U, W = gpu.get_state()
     lam = U.copy()
-    st = inputs.random_state(0, Lx, Lz, 16, 252, 16, 1, 0.05, 5, spectrum="low")
+    st = inputs.random_state(0, Lx, Lz, 16, 254, 16, 1, 0.05, 5, spectrum="low")
     gpu.set_state(*st, member0=1)
     gpu.step(5)
     v, eta, U, W = gpu.get_state()
