@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", choices=["mixed", "fp64", "3xbf16"], default="mixed")
+    ap.add_argument("--precision", choices=["mixed", "fp64", "3xbf16", "fp32mm"], default="mixed")
     ap.add_argument("--workload", default="channel-re4200-64x97x64-e16")
     ap.add_argument("--ensemble", type=int, default=None)
     ap.add_argument("--no-graph", action="store_true")
@@ -256,7 +256,7 @@ def main():
     ens = dns.Ensemble(w["flow"], w["Re"], w["Lx"], w["Lz"], w["Nx"], w["Ny"], w["Nz"], E, w["dt"])
     ens.set_stream(stream)
     ens_precision = {"fp64": dns.PREC_FP64, "mixed": dns.PREC_MIXED_FP32,
-                     "3xbf16": dns.PREC_MIXED_3XBF16}[args.precision]
+                     "3xbf16": dns.PREC_MIXED_3XBF16, "fp32mm": dns.PREC_MIXED_FP32MM}[args.precision]
     ens.set_precision(ens_precision)
     ens.set_option(dns.OPT_GRAPH, 0 if args.no_graph else 1)
     forms = {"advective": dns.ADV_ADVECTIVE, "rotational": dns.ADV_ROTATIONAL}
@@ -367,7 +367,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "f32+f64", "3xbf16": "f32+bf16x3+f64", "fp64": "f64"}[args.precision],
+        "dtype": {"mixed": "f32+f64", "3xbf16": "f32+bf16x3+f64", "fp32mm": "f32+f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": name, "flow": "poiseuille" if w["flow"] else "couette",
                    "Re": w["Re"], "grid": f"{w['Nx']}x{w['Ny']}x{w['Nz']}", "ensemble": E,

@@ -206,6 +206,10 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                   products (D1 and the clamped D1c) on BF16
                                   matrix cores as three split products
                                   (hi*hi + hi*lo + lo*hi, FP32 accumulation)       */
+#define DNS_PREC_MIXED_FP32MM 3 /* as DNS_PREC_MIXED_FP32, with the y-derivative
+                                  products on FP32 matrix cores (FP32 operators
+                                  and operands, FP32 accumulation): FFTs and
+                                  derivative products in FP32, solves in FP64      */
 
 /* Set an option.  Precision may be changed between steps (the stage buffers
  * are re-derived from the FP64 state).  Errors: DNS_E_INVALID. */

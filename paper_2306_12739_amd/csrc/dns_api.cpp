@@ -52,6 +52,7 @@ struct dns_handle {
   double *D1intT_e = nullptr, *D1intT_o = nullptr, *D1cT_e = nullptr, *D1cT_o = nullptr;
   double *D1T_e = nullptr, *D1T_o = nullptr;
   unsigned short *Dhi[6] = {}, *Dlo[6] = {};  // split-BF16 tiles of the six derivative halves
+  float* Df[6] = {};                            // FP32 tiles of the six derivative halves
   int CRP = 16, SR = 0, TR = 0;
   double *lift_h[2] = {nullptr, nullptr}, *green_h[2] = {nullptr, nullptr};
   double *ccw_h = nullptr, *D1 = nullptr, *ccw = nullptr;
@@ -175,6 +176,7 @@ void free_all(dns_handle* h) {
   for (int i = 0; i < 6; ++i) {
     if (h->Dhi[i]) hipFree(h->Dhi[i]);
     if (h->Dlo[i]) hipFree(h->Dlo[i]);
+    if (h->Df[i]) hipFree(h->Df[i]);
   }
   if (h->own_stream) hipStreamDestroy(h->own_stream);
 }
@@ -246,6 +248,7 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   for (int i = 0; i < 6; ++i) {
     a.Dhi[i] = h->Dhi[i];
     a.Dlo[i] = h->Dlo[i];
+    a.Df[i] = h->Df[i];
   }
   a.lift_h = h->lift_h[hi];
   a.green_h = h->green_h[hi];
@@ -874,15 +877,18 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     green_h[hi] = halves(ho.green[hi]);
   }
   // derivative halves: even input -> odd output and odd input -> even output,
-  // FP64 tiles and split-BF16 tiles (index order of ModeArgs::Dhi)
+  // FP64 tiles, split-BF16 tiles and FP32 tiles (index order of ModeArgs::Dhi)
   std::vector<unsigned short> bhi[6], blo[6];
+  std::vector<float> bf32[6];
   int nsplit = 0;
   auto dhalf = [&](const double* M, int rows_out, int Cn, int ldm, bool even_in) {
     const std::vector<double> b = half_block(M, rows_out, Cn, ldm, even_in);
     const int ncol = even_in ? (Cn + 1) / 2 : Cn / 2;
     tile_for_mfma_bf16(b.data(), rows_out, ncol, ncol, &bhi[nsplit], &blo[nsplit]);
+    std::vector<double> t = tile_for_mfma(b.data(), rows_out, ncol, ncol);
+    bf32[nsplit].assign(t.begin(), t.end());  // the same A lane order, rounded to FP32
     ++nsplit;
-    return tile_for_mfma(b.data(), rows_out, ncol, ncol);
+    return t;
   };
   const double* D1int = ho.D1.data() + My;  // interior rows of D1
   const std::vector<double> D1intT_e = dhalf(D1int, Ho, My, My, true);
@@ -910,6 +916,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   for (int i = 0; i < 6; ++i) {
     ALLOC(h->Dhi[i], bhi[i].size());
     ALLOC(h->Dlo[i], blo[i].size());
+    ALLOC(h->Df[i], bf32[i].size());
   }
   ALLOC(h->D1, ho.D1.size());
   ALLOC(h->ccw, ho.ccw.size());
@@ -958,6 +965,8 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   for (int i = 0; i < 6; ++i) {
     ok &= hipMemcpy(h->Dhi[i], bhi[i].data(), bhi[i].size() * 2, hipMemcpyHostToDevice) == hipSuccess;
     ok &= hipMemcpy(h->Dlo[i], blo[i].data(), blo[i].size() * 2, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(h->Df[i], bf32[i].data(), bf32[i].size() * sizeof(float), hipMemcpyHostToDevice) ==
+          hipSuccess;
   }
   ok &= up(h->D1, ho.D1) == hipSuccess;
   ok &= up(h->ccw, ho.ccw) == hipSuccess;
@@ -1064,7 +1073,8 @@ int dns_set_option(dns_handle* h, int key, long long value) {
   }
   switch (key) {
     case DNS_OPT_PRECISION:
-      if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32 && value != DNS_PREC_MIXED_3XBF16)
+      if (value != DNS_PREC_FP64 && value != DNS_PREC_MIXED_FP32 && value != DNS_PREC_MIXED_3XBF16 &&
+          value != DNS_PREC_MIXED_FP32MM)
         return fail(h, DNS_E_INVALID, "unknown precision");
       if (!form_fits(h, int(value), plane_form(h)))
         return fail(h, DNS_E_UNSUPPORTED, "no advection-kernel variant of this form fits this grid at that precision");

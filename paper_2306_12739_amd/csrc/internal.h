@@ -69,6 +69,9 @@ struct ModeArgs {
   // precision, index order D1int_e, D1int_o, D1c_e, D1c_o, D1_e, D1_o
   const unsigned short* Dhi[6];
   const unsigned short* Dlo[6];
+  // the same six halves in FP32, in the A lane order of the FP64 tiles (the
+  // FP32 matrix-core precision)
+  const float* Df[6];
   const double* lift_h;    // [N]: even half (He) then odd half (Ho) of the Couette lift
   const double* green_h;   // [N]: halves of the pressure-gradient response
   const double* ccw_h;     // [Fe]: Clenshaw-Curtis weights summed over node pairs

@@ -30,8 +30,8 @@
 // 64 consecutive doubles, lane l holding M[16 rt + l % 16][4 kt + l / 16]), so
 // each A fragment is one coalesced 512 B load; X lives in LDS as [k][column].
 // With the split-BF16 precision the six y-derivative contractions instead run
-// as three bfloat16 products on v_mfma_f32_16x16x16bf16_1k (the solves stay
-// FP64).
+// as three bfloat16 products on v_mfma_f32_16x16x16bf16_1k, and with the FP32
+// matrix-core precision on v_mfma_f32_16x16x4f32 (the solves stay FP64).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -313,13 +313,51 @@ __device__ __forceinline__ void mfma_contract_split(const unsigned short* __rest
   }
 }
 
-// A y-derivative contraction (one of the six parity halves, index `which`):
-// FP64 matrix cores, or the split-BF16 variant.  Kd is the K dimension.
-template <bool kSplit, class Store>
+// FP32 variant of mfma_contract: M in FP32, in the A lane order of the FP64
+// tiles (K = 4 KT), X rounded to FP32, FP32 accumulation on
+// v_mfma_f32_16x16x4f32.  D layout: lane l, register r -> row 4 (l / 16) + r,
+// col l % 16.
+template <class Store>
+__device__ __forceinline__ void mfma_contract_f32(const float* __restrict__ Mt, int RT, int KT, const double* X,
+                                                  int ldx, int CT, Store store) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < RT * CT; t += kWaves) {
+    const int rt = t / CT, ct = t - rt * CT;
+    const float* a = Mt + size_t(rt) * KT * 64 + lane;
+    const double* b = X + lk * ldx + ct * 16 + lr;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    int kt = 0;
+    for (; kt + 4 <= KT; kt += 4) {
+      float p[4], x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = a[(kt + u) * 64];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = float(b[(4 * (kt + u)) * ldx]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(p[u], x[u], acc, 0, 0, 0);
+    }
+    for (; kt < KT; ++kt)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kt * 64], float(b[4 * kt * ldx]), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(rt * 16 + 4 * lk + r, ct * 16 + lr, double(acc[r]));
+  }
+}
+
+// y-derivative arithmetic of the per-mode kernel: FP64 matrix cores, split
+// BF16 (three bfloat16 products) or FP32 matrix cores
+constexpr int kDerFP64 = 0, kDerSplitBF16 = 1, kDerFP32 = 2;
+
+// A y-derivative contraction (one of the six parity halves, index `which`).
+// Kd is the K dimension.
+template <int kDer, class Store>
 __device__ __forceinline__ void dcontract(const ModeArgs& a, int which, const double* Mt, int RT, int Kd,
                                           const double* X, int ldx, int CT, Store store) {
-  if constexpr (kSplit)
+  if constexpr (kDer == kDerSplitBF16)
     mfma_contract_split(a.Dhi[which], a.Dlo[which], RT, (Kd + 15) / 16, X, ldx, CT, store);
+  else if constexpr (kDer == kDerFP32)
+    mfma_contract_f32(a.Df[which], RT, (Kd + 3) / 4, X, ldx, CT, store);
   else
     mfma_contract(Mt, RT, (Kd + 3) / 4, X, ldx, CT, store);
 }
@@ -352,7 +390,7 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 //   T  : Q = i kx N_u + i kz N_w (FH), later v (FH), later du/dy (FH)
 // The per-mode work of workgroup `flat` (a group and member tile) of the
 // launch described by `a`.
-template <typename VT, bool kSplit, bool kForce>
+template <typename VT, int kDer, bool kForce>
 __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
@@ -483,11 +521,11 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
       __syncthreads();
       // F = -k^2 N_v - D1 Q: odd F from even Q, even F from odd Q
-      if constexpr (kSplit) {
-        dcontract<kSplit>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+      if constexpr (kDer != kDerFP64) {
+        dcontract<kDer>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
         });
-        dcontract<kSplit>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        dcontract<kDer>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
           if (r < He) S[(He + r) * CRP + cc] -= v;
         });
       } else {
@@ -717,11 +755,11 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     }
     __syncthreads();
     // ---- velocity recovery: dv/dy = D1c v (odd <- even, even <- odd) -> S2 FH
-    if constexpr (kSplit) {
-      dcontract<kSplit>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+    if constexpr (kDer != kDerFP64) {
+      dcontract<kDer>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kSplit>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) S2[r * CRP + cc] = v;
       });
     } else {
@@ -782,7 +820,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     const CJob jd[4] = {{a.D1T_e, RFo, (Fe + 3) / 4, S2}, {a.D1T_o, RFe, (Fo + 3) / 4, S2 + size_t(Fe) * CRP},
                         {a.D1T_e, RFo, (Fe + 3) / 4, S}, {a.D1T_o, RFe, (Fo + 3) / 4, S + size_t(Fe) * CRP}};
     bool merged = false;
-    if constexpr (!kSplit) {
+    if constexpr (kDer == kDerFP64) {
       if (mfma_jobs_fit(jd, CT)) {
         mfma_jobs<true>(jd, CRP, CT, [&](int j, int r, int cc, double v) {
           const int lim = (j & 1) ? Fe : Fo;
@@ -792,17 +830,17 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
     }
     if (!merged) {
-      dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) T[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) T[r * CRP + cc] = v;
       });
       __syncthreads();
-      dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) S2[r * CRP + cc] = v;
       });
     }
@@ -853,10 +891,10 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     }
     __syncthreads();
     // (E_U, E_W) = -D1 (<uv>, <wv>) on interior halves
-    dcontract<kSplit>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kDer>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
       if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] = -v;
     });
-    dcontract<kSplit>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kDer>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < He) S[(He + r) * CRP + cc] = -v;
     });
     __syncthreads();
@@ -980,10 +1018,10 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   }
   __syncthreads();
   // (0,0) velocity fields: u = U, v = 0, w = W, du/dy = D1 U, dw/dy = D1 W
-  dcontract<kSplit>(a, 4, a.D1T_e, RFo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kDer>(a, 4, a.D1T_e, RFo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
     if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
   });
-  dcontract<kSplit>(a, 5, a.D1T_o, RFe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kDer>(a, 5, a.D1T_o, RFe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
     if (r < Fe) S2[r * CRP + cc] = v;
   });
   __syncthreads();
@@ -1010,21 +1048,21 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
 
 // Four waves per SIMD (registers <= 128): two workgroups of eight waves per CU
 // when their LDS allows.
-template <typename VT, bool kSplit, bool kForce>
+template <typename VT, int kDer, bool kForce>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) mode_kernel(ModeArgs a) {
-  mode_body<VT, kSplit, kForce>(a, xcd_logical_m(blockIdx.x, gridDim.x));
+  mode_body<VT, kDer, kForce>(a, xcd_logical_m(blockIdx.x, gridDim.x));
 }
 
 // Several ensembles' per-mode work in one launch (uneven grouped ensembles,
 // members of different Re and grid): workgroups [first[d], first[d + 1]) run
 // descriptor d, each with the launch shape it would have alone.
-template <typename VT, bool kSplit, bool kForce>
+template <typename VT, int kDer, bool kForce>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) mode_grouped_kernel(const ModeArgs* __restrict__ descs,
                                                            const int* __restrict__ first, int ndesc) {
   const int b = blockIdx.x;
   int d = 0;
   while (d + 1 < ndesc && b >= first[d + 1]) ++d;
-  mode_body<VT, kSplit, kForce>(descs[d], xcd_logical_m(b - first[d], first[d + 1] - first[d]));
+  mode_body<VT, kDer, kForce>(descs[d], xcd_logical_m(b - first[d], first[d + 1] - first[d]));
 }
 
 // LDS geometry of one workgroup; shared with the host launcher.
@@ -1060,26 +1098,32 @@ int mode_member_tile(int My, int E) {
 }
 
 namespace {
+// precision 0: FP64 stage buffers; 1: FP32 stage buffers; 2: FP32 stage
+// buffers and split-BF16 derivative products; 3: FP32 stage buffers and FP32
+// matrix-core derivative products
 template <bool kForce>
 const void* mode_fn(int precision) {
-  return precision == 0   ? reinterpret_cast<const void*>(&mode_kernel<double, false, kForce>)
-         : precision == 1 ? reinterpret_cast<const void*>(&mode_kernel<float, false, kForce>)
-                          : reinterpret_cast<const void*>(&mode_kernel<float, true, kForce>);
+  switch (precision) {
+    case 0: return reinterpret_cast<const void*>(&mode_kernel<double, kDerFP64, kForce>);
+    case 1: return reinterpret_cast<const void*>(&mode_kernel<float, kDerFP64, kForce>);
+    case 2: return reinterpret_cast<const void*>(&mode_kernel<float, kDerSplitBF16, kForce>);
+    default: return reinterpret_cast<const void*>(&mode_kernel<float, kDerFP32, kForce>);
+  }
 }
-}  // namespace
-
-namespace {
 template <bool kForce>
 const void* mode_grouped_fn(int precision) {
-  return precision == 0   ? reinterpret_cast<const void*>(&mode_grouped_kernel<double, false, kForce>)
-         : precision == 1 ? reinterpret_cast<const void*>(&mode_grouped_kernel<float, false, kForce>)
-                          : reinterpret_cast<const void*>(&mode_grouped_kernel<float, true, kForce>);
+  switch (precision) {
+    case 0: return reinterpret_cast<const void*>(&mode_grouped_kernel<double, kDerFP64, kForce>);
+    case 1: return reinterpret_cast<const void*>(&mode_grouped_kernel<float, kDerFP64, kForce>);
+    case 2: return reinterpret_cast<const void*>(&mode_grouped_kernel<float, kDerSplitBF16, kForce>);
+    default: return reinterpret_cast<const void*>(&mode_grouped_kernel<float, kDerFP32, kForce>);
+  }
 }
 }  // namespace
 
 // Resolve the per-mode kernel instantiations on the current device.
 hipError_t mode_preload() {
-  for (int prec = 0; prec < 3; ++prec) {
+  for (int prec = 0; prec < 4; ++prec) {
     for (const void* fn : {mode_fn<false>(prec), mode_fn<true>(prec), mode_grouped_fn<false>(prec),
                            mode_grouped_fn<true>(prec)}) {
       hipFuncAttributes attr;
@@ -1090,8 +1134,7 @@ hipError_t mode_preload() {
   return hipSuccess;
 }
 
-// precision 0: FP64 stage buffers; 1: FP32 stage buffers; 2: FP32 stage
-// buffers and split-BF16 derivative products.  A forcing (a.fv) selects the
+// The kernel of the precision (as mode_fn); a forcing (a.fv) selects the
 // variant that subtracts it.
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   const int nblk = a.G * a.ntiles;

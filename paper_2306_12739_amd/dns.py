@@ -49,6 +49,7 @@ ADV_ROTATIONAL = 1
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1
 PREC_MIXED_3XBF16 = 2
+PREC_MIXED_FP32MM = 3
 
 EXPORTED = ["dns_create", "dns_set_option", "dns_set_state", "dns_get_state", "dns_step",
             "dns_stats", "dns_stats_reset", "dns_sync", "dns_destroy", "dns_last_error",

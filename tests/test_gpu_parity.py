@@ -66,12 +66,13 @@ def test_stage0_intermediates_fp64():
     gpu.close()
 
 
-@pytest.mark.parametrize("precision", [dns.PREC_MIXED_FP32, dns.PREC_MIXED_3XBF16])
+@pytest.mark.parametrize("precision", [dns.PREC_MIXED_FP32, dns.PREC_MIXED_3XBF16, dns.PREC_MIXED_FP32MM])
 @pytest.mark.parametrize("grid", [(16, 33, 0.1, "low"), (64, 97, 0.3, "k2")])
 def test_stage0_intermediates_mixed_per_field(grid, precision):
     """Error of the mixed-precision paths against the FP64 oracle, per field:
-    velocity fields are formed with FP64 (or split-BF16) y-derivative products
-    and stored in FP32; the advection terms come from FP32 transforms."""
+    velocity fields are formed with FP64 (split-BF16, or FP32 matrix-core)
+    y-derivative products and stored in FP32; the advection terms come from
+    FP32 transforms."""
     n, Ny, amp, spec = grid
     flow = 0 if n == 16 else 1
     Lx, Lz = (1.75 * np.pi, 1.2 * np.pi) if flow == 0 else (2.0 * np.pi, np.pi)
@@ -87,9 +88,10 @@ def test_stage0_intermediates_mixed_per_field(grid, precision):
     errs["<uv>"] = rel(means[0], uv)
     errs["<wv>"] = rel(means[1], wv)
     say("  relative 2-norm errors:", {k: f"{v:.1e}" for k, v in errs.items()})
-    # split-BF16: the products accumulate in FP32, and D1 at Ny = 97 has entries
-    # ~ (Ny-1)^2 / 3, so y-derivatives carry ~1e-3 relative error (measured 1.1e-3)
-    split = precision == dns.PREC_MIXED_3XBF16
+    # split-BF16 and FP32 matrix cores: the products accumulate in FP32, and D1
+    # at Ny = 97 has entries ~ (Ny-1)^2 / 3, so y-derivatives carry ~1e-3
+    # relative error (split-BF16 measured 1.1e-3)
+    split = precision in (dns.PREC_MIXED_3XBF16, dns.PREC_MIXED_FP32MM)
     for f in ("u", "v", "w", "uy", "wy"):
         assert errs[f] <= (3e-3 if split else 1e-7), f
     for f in ("Nu", "Nv", "Nw", "<uv>", "<wv>"):
@@ -477,7 +479,7 @@ def test_time_averaged_statistics_match_oracle():
     gpu.close()
 
 
-@pytest.mark.parametrize("precision", [dns.PREC_MIXED_FP32, dns.PREC_MIXED_3XBF16])
+@pytest.mark.parametrize("precision", [dns.PREC_MIXED_FP32, dns.PREC_MIXED_3XBF16, dns.PREC_MIXED_FP32MM])
 def test_mixed_precision_error_is_small(precision):
     say(f"case: precision {precision}, couette 16x33x16, 100 steps; errors vs FP64 oracle")
     gpu, ref = cfg1_pair()
@@ -491,7 +493,7 @@ def test_mixed_precision_error_is_small(precision):
     ref.step(100)
     errs = field_errors(gpu, ref, ref.laminar_profile()[None, :])
     say("mixed errors after 100 steps:", errs)
-    split = precision == dns.PREC_MIXED_3XBF16
+    split = precision in (dns.PREC_MIXED_3XBF16, dns.PREC_MIXED_FP32MM)
     assert max(e_stage.values()) <= (1e-4 if split else 1e-5)
     assert max(errs[k] for k in ("v", "eta", "U-Ulam", "W")) <= (1e-3 if split else 1e-4)
     gpu.close()

@@ -99,20 +99,23 @@ def compare(a, b):
 
 @pytest.mark.parametrize("name", ["couette-re600-32x49x32-e64", "channel-re4200-64x97x64-e16"])
 def test_mixed_statistics_match_fp64(name):
-    say(f"case: statistics {name}: FP64, mixed, split-BF16, FP64 with another seed")
+    say(f"case: statistics {name}: FP64, mixed, split-BF16, FP32 matrix cores, FP64 with another seed")
     ref = run(name, dns.PREC_FP64)
     mix = run(name, dns.PREC_MIXED_FP32)
     spl = run(name, dns.PREC_MIXED_3XBF16)
+    f32 = run(name, dns.PREC_MIXED_FP32MM)
     other = run(name, dns.PREC_FP64, seed=inputs.WORKLOADS[name]["seed"] + 100)
     d_mix = compare(mix, ref)
     d_spl = compare(spl, ref)
+    d_f32 = compare(f32, ref)
     d_seed = compare(other, ref)
     rec = {"workload": name, "mixed_vs_fp64": d_mix, "split_bf16_vs_fp64": d_spl,
-           "fp64_seed_to_seed": d_seed,
+           "fp32_matrix_vs_fp64": d_f32, "fp64_seed_to_seed": d_seed,
            "re_tau_fp64": ref["re_tau"], "re_tau_mixed": mix["re_tau"], "re_tau_split": spl["re_tau"],
            "seconds_fp64": ref["seconds"], "seconds_mixed": mix["seconds"],
            "seconds_split": spl["seconds"],
-           "failed": int(ref["failed"].sum() + mix["failed"].sum() + spl["failed"].sum())}
+           "seconds_fp32_matrix": f32["seconds"],
+           "failed": int(ref["failed"].sum() + mix["failed"].sum() + spl["failed"].sum() + f32["failed"].sum())}
     # the FP64 run's own sampling error: bootstrap over members of the pooled
     # statistics, from the library's per-member time averages
     rng = np.random.default_rng(0)
@@ -127,6 +130,7 @@ def test_mixed_statistics_match_fp64(name):
     for k in ("U", "urms", "vrms", "wrms", "tau_w"):
         assert d_mix[k] <= 0.01, (k, d_mix[k])
         assert d_spl[k] <= 0.01, (k, d_spl[k])
+        assert d_f32[k] <= 0.01, (k, d_f32[k])
 
 
 DECOR = {"name": "couette-re600-32x49x32-e64", "spinup": 3000, "decorrelate": 6000, "window": 8000}
