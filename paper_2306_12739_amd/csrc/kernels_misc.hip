@@ -6,6 +6,8 @@
 // and power input follow from the momentum equation between walls (Sec. 2).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace dns {
@@ -69,27 +71,60 @@ int grid_for(size_t n) {
   return int(b);
 }
 
-// One thread per member: volume integrals with Clenshaw-Curtis weights
-// (fixed summation order), wall shear, power input, finiteness, and the
-// optional time accumulation of the plane profiles.
-__global__ void stats_kernel(StatsArgs a, int accumulate) {
-  const int e = a.e0 + int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (e >= a.e0 + a.ec) return;
-  const int My = a.My, E = a.E;
-  double en = 0.0, ds = 0.0, q = 0.0, dlo = 0.0, dhi = 0.0;
-  for (int j = 0; j < My; ++j) {
-    const size_t je = size_t(j) * E + e;
-    const double w = a.ccw[j];
-    en += w * (a.psum[size_t(PS_UU) * My * E + je] + a.psum[size_t(PS_VV) * My * E + je] +
-               a.psum[size_t(PS_WW) * My * E + je]);
-    ds += w * a.psum[size_t(PS_GRAD) * My * E + je];
-    q += w * a.U[je];
-    dlo += a.D1[j] * a.U[je];
-    dhi += a.D1[size_t(My - 1) * My + j] * a.U[je];
+// Sum of x over the workgroup in a fixed order (a butterfly within each wave,
+// then the waves in order): the same value in every thread after the call.
+constexpr int kStatsThreads = 256;
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&x)[NV], double (*red)[kStatsThreads / 64]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    for (int off = 32; off > 0; off >>= 1) x[c] += __shfl_xor(x[c], off, 64);
+    if (lane == 0) red[c][wv] = x[c];
   }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    double t = 0.0;
+    for (int w = 0; w < kStatsThreads / 64; ++w) t += red[c][w];
+    x[c] = t;
+  }
+}
+
+// One workgroup per member, one node per thread: volume integrals with
+// Clenshaw-Curtis weights (fixed summation order), wall shear, power input,
+// finiteness, and the optional time accumulation of the plane profiles.
+__global__ void __launch_bounds__(kStatsThreads) stats_kernel(StatsArgs a, int accumulate) {
+  const int e = a.e0 + int(blockIdx.x);
+  const int My = a.My, E = a.E;
+  const size_t ME = size_t(My) * E;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // energy, dissipation, flux, lower and upper shear
+  for (int j = threadIdx.x; j < My; j += kStatsThreads) {
+    const size_t je = size_t(j) * E + e;
+    const double w = a.ccw[j], U = a.U[je];
+    s[0] += w * (a.psum[size_t(PS_UU) * ME + je] + a.psum[size_t(PS_VV) * ME + je] +
+                 a.psum[size_t(PS_WW) * ME + je]);
+    s[1] += w * a.psum[size_t(PS_GRAD) * ME + je];
+    s[2] += w * U;
+    s[3] += a.D1[j] * U;
+    s[4] += a.D1[size_t(My - 1) * My + j] * U;
+    if (accumulate) {
+      const double W = a.W[je];
+      a.acc[size_t(PA_U) * ME + je] += U;
+      a.acc[size_t(PA_W) * ME + je] += W;
+      a.acc[size_t(PA_U2) * ME + je] += U * U;
+      a.acc[size_t(PA_W2) * ME + je] += W * W;
+      a.acc[size_t(PA_UU) * ME + je] += a.psum[size_t(PS_UU) * ME + je];
+      a.acc[size_t(PA_VV) * ME + je] += a.psum[size_t(PS_VV) * ME + je];
+      a.acc[size_t(PA_WW) * ME + je] += a.psum[size_t(PS_WW) * ME + je];
+      a.acc[size_t(PA_UV) * ME + je] += a.means[je];
+    }
+  }
+  __shared__ double red[5][kStatsThreads / 64];
+  block_sum(s, red);
+  if (threadIdx.x != 0) return;
   const double Ly = 2.0;
-  en = 0.5 * en / Ly;
-  ds = ds / (a.Re * Ly);
+  const double en = 0.5 * s[0] / Ly, ds = s[1] / (a.Re * Ly), q = s[2], dlo = s[3], dhi = s[4];
   const double pin = a.poiseuille != 0.0 ? a.gamma[e] * q / Ly : a.Uw * (dhi + dlo) / (a.Re * Ly);
   double* inst = a.inst;
   inst[DI_E * E + e] = en;
@@ -100,21 +135,9 @@ __global__ void stats_kernel(StatsArgs a, int accumulate) {
   inst[DI_THI * E + e] = dhi / a.Re;
   if (!isfinite(en) || !isfinite(ds) || !isfinite(q)) a.failed[e] = 1;
   if (accumulate) {
-    for (int j = 0; j < My; ++j) {
-      const size_t je = size_t(j) * E + e;
-      const double U = a.U[je], W = a.W[je];
-      a.acc[size_t(PA_U) * My * E + je] += U;
-      a.acc[size_t(PA_W) * My * E + je] += W;
-      a.acc[size_t(PA_U2) * My * E + je] += U * U;
-      a.acc[size_t(PA_W2) * My * E + je] += W * W;
-      a.acc[size_t(PA_UU) * My * E + je] += a.psum[size_t(PS_UU) * My * E + je];
-      a.acc[size_t(PA_VV) * My * E + je] += a.psum[size_t(PS_VV) * My * E + je];
-      a.acc[size_t(PA_WW) * My * E + je] += a.psum[size_t(PS_WW) * My * E + je];
-      a.acc[size_t(PA_UV) * My * E + je] += a.means[je];
-    }
     // wall shear for tau_w: accumulate in the extra slot after the profiles
-    a.acc[size_t(NPA) * My * E + e] += dlo;
-    a.acc[size_t(NPA) * My * E + E + e] += dhi;
+    a.acc[size_t(NPA) * ME + e] += dlo;
+    a.acc[size_t(NPA) * ME + E + e] += dhi;
   }
 }
 
@@ -191,16 +214,18 @@ __global__ void share_columns(double* __restrict__ v, double* __restrict__ eta, 
 // no-slip wall only U00 and the wall shears du/dy, dw/dy contribute; the
 // general expressions are evaluated anyway.  One workgroup per (member, wall),
 // fixed-order reduction.
+constexpr int kWallThreads = 256;
 template <typename VT>
-__global__ void __launch_bounds__(256) wall_sums(const VT* __restrict__ vel, double* __restrict__ psum,
-                                                 double* __restrict__ means, int My, int E, int K, int NZ,
-                                                 int P, double kxs, double kzs, int e0) {
+__global__ void __launch_bounds__(kWallThreads) wall_sums(const VT* __restrict__ vel, double* __restrict__ psum,
+                                                          double* __restrict__ means, int My, int E, int K, int NZ,
+                                                          int P, double kxs, double kzs, int e0) {
+  typedef typename std::conditional<sizeof(VT) == 4, float2, double2>::type P2;
   const int e = e0 + int(blockIdx.x >> 1);
   const int j = (blockIdx.x & 1) ? My - 1 : 0;
   const size_t FS = 2 * size_t(My) * E * K;  // field stride (VT units)
   const VT* row = vel + 2 * ((size_t(j) * E + e) * K);
   double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // uu vv ww grad uv wv
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+  auto add = [&](int k, const P2 (&g)[5]) {
     const int nx = k / NZ, iz = k - nx * NZ;
     const int nz = iz < P ? iz : iz - NZ;
     const double m = nx == 0 ? 1.0 : 2.0;
@@ -208,8 +233,8 @@ __global__ void __launch_bounds__(256) wall_sums(const VT* __restrict__ vel, dou
     double f[5][2];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      f[c][0] = double(row[c * FS + 2 * k]);
-      f[c][1] = double(row[c * FS + 2 * k + 1]);
+      f[c][0] = double(g[c].x);
+      f[c][1] = double(g[c].y);
     }
     const double uu = f[0][0] * f[0][0] + f[0][1] * f[0][1];
     const double vv = f[1][0] * f[1][0] + f[1][1] * f[1][1];
@@ -223,8 +248,21 @@ __global__ void __launch_bounds__(256) wall_sums(const VT* __restrict__ vel, dou
     q[3] += m * (k2 * (uu + vv + ww) + uy + wy + vr * vr + vi * vi);
     q[4] += m * (f[0][0] * f[1][0] + f[0][1] * f[1][1]);
     q[5] += m * (f[2][0] * f[1][0] + f[2][1] * f[1][1]);
+  };
+  // two modes per thread loaded together (the second clamped to mode 0 and
+  // not summed when it is past K)
+  for (int k = threadIdx.x; k < K; k += 2 * kWallThreads) {
+    const int k2 = k + kWallThreads < K ? k + kWallThreads : 0;
+    P2 ga[5], gb[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      ga[c] = *reinterpret_cast<const P2*>(row + c * FS + 2 * k);
+      gb[c] = *reinterpret_cast<const P2*>(row + c * FS + 2 * k2);
+    }
+    add(k, ga);
+    if (k + kWallThreads < K) add(k2, gb);
   }
-  __shared__ double red[6][4];
+  __shared__ double red[6][kWallThreads / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -235,7 +273,10 @@ __global__ void __launch_bounds__(256) wall_sums(const VT* __restrict__ vel, dou
   __syncthreads();
   if (threadIdx.x == 0) {
     double t[6];
-    for (int c = 0; c < 6; ++c) t[c] = red[c][0] + red[c][1] + red[c][2] + red[c][3];
+    for (int c = 0; c < 6; ++c) {
+      t[c] = 0.0;
+      for (int w = 0; w < kWallThreads / 64; ++w) t[c] += red[c][w];
+    }
     const size_t je = size_t(j) * E + e, ME = size_t(My) * E;
     psum[size_t(PS_UU) * ME + je] = t[0];
     psum[size_t(PS_VV) * ME + je] = t[1];
@@ -251,10 +292,10 @@ __global__ void __launch_bounds__(256) wall_sums(const VT* __restrict__ vel, dou
 hipError_t launch_wall_sums(int precision, const void* vel, double* psum, double* means, int My, int E, int K,
                             int NZ, int P, double kxs, double kzs, int e0, int ec, hipStream_t s) {
   if (precision == 0)
-    hipLaunchKernelGGL(wall_sums<double>, dim3(2 * ec), dim3(256), 0, s, static_cast<const double*>(vel), psum,
+    hipLaunchKernelGGL(wall_sums<double>, dim3(2 * ec), dim3(kWallThreads), 0, s, static_cast<const double*>(vel), psum,
                        means, My, E, K, NZ, P, kxs, kzs, e0);
   else
-    hipLaunchKernelGGL(wall_sums<float>, dim3(2 * ec), dim3(256), 0, s, static_cast<const float*>(vel), psum,
+    hipLaunchKernelGGL(wall_sums<float>, dim3(2 * ec), dim3(kWallThreads), 0, s, static_cast<const float*>(vel), psum,
                        means, My, E, K, NZ, P, kxs, kzs, e0);
   return hipGetLastError();
 }
@@ -327,7 +368,8 @@ hipError_t misc_preload() {
 }
 
 hipError_t launch_stats(const StatsArgs& a, int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL(stats_kernel, dim3((a.ec + 63) / 64), dim3(64), 0, s, a, accumulate);
+  if (a.ec < 1) return hipSuccess;
+  hipLaunchKernelGGL(stats_kernel, dim3(a.ec), dim3(kStatsThreads), 0, s, a, accumulate);
   return hipGetLastError();
 }
 

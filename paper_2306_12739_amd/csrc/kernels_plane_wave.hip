@@ -136,20 +136,26 @@ __device__ __forceinline__ cx<T> root_s(int bc, int sgn) {
 //   inverse (decimation in frequency): v <- (sgn v + v[l ^ H]) * tw
 //   forward (decimation in time):      t = v * conj(tw); v <- sgn t + t[l ^ H]
 // with sgn = -1, tw = e^{2 pi i (l mod H) / (2H)} in the upper lane of a pair
-// and sgn = +1, tw = 1 in the lower one.
+// and sgn = +1, tw = 1 in the lower one.  At span 1 the twiddle is 1 in every
+// lane and is not applied.
 template <typename T, int H>
 __device__ __forceinline__ void stage_inv(cx<T>* v, cx<T> tw, T sgn) {
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
     const T px = lane_xor<H>(v[n].x), py = lane_xor<H>(v[n].y);
-    v[n] = cmul(cx<T>{sgn * v[n].x + px, sgn * v[n].y + py}, tw);
+    const cx<T> s{sgn * v[n].x + px, sgn * v[n].y + py};
+    if constexpr (H == 1)
+      v[n] = s;
+    else
+      v[n] = cmul(s, tw);
   }
 }
 template <typename T, int H>
 __device__ __forceinline__ void stage_fwd(cx<T>* v, cx<T> tw, T sgn) {
 #pragma unroll
   for (int n = 0; n < 3; ++n) {
-    const cx<T> t = cmul(v[n], cconj(tw));
+    cx<T> t = v[n];
+    if constexpr (H != 1) t = cmul(t, cconj(tw));
     const T px = lane_xor<H>(t.x), py = lane_xor<H>(t.y);
     v[n] = cx<T>{sgn * t.x + px, sgn * t.y + py};
   }
