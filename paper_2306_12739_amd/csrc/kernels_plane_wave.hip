@@ -111,7 +111,8 @@ struct WaveCfg {
   static constexpr int YP = PP + 1;                 // forward z output [f][nx][k] pitch
   static constexpr int AZY = 8 * L * ZYP, AZB = 8 * PP * ZP, AZF = 3 * PH * FP, AY = 3 * L * YP;
   static constexpr int A = AZY > AZB ? (AZY > AZF + AY ? AZY : AZF + AY) : (AZB > AZF + AY ? AZB : AZF + AY);
-  static constexpr int NACC = (3 * K + NT - 1) / NT;
+  static constexpr int NM = (K + NT - 1) / NT;      // kept modes per thread
+  static constexpr int NACC = 3 * NM;               // (field, mode) accumulators per thread
   static constexpr size_t kLdsBytes = size_t(A + MX + MZ) * 2 * sizeof(T) + 6 * (NT / 64) * sizeof(double);
   static_assert((L & (L - 1)) == 0 && L >= 8 && L <= 32, "row-pair lanes: a power of two, 8..32");
   static_assert(PP % 16 == 0 && MZ % PP == 0 && S >= 1 && S <= 3, "chunk rows: 16, 32 or 48 dividing Mz");
@@ -433,28 +434,31 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
       for (int kk = 0; kk < 16; ++kk) out[S * kk + c] = z[kk];
     }
     __syncthreads();
-    // the accumulators' (field, mode) indices are recomputed in every chunk
-    // rather than held in registers across the chunk loop
+    // the accumulators' mode indices are recomputed in every chunk rather than
+    // held in registers across the chunk loop; one mode's index arithmetic and
+    // twiddle serve its three fields
     int tbase = tid;
     asm volatile("" : "+v"(tbase));
 #pragma unroll
-    for (int k = 0; k < Cfg::NACC; ++k) {
-      const int idx = tbase + k * NT;
-      if (idx < 3 * K) {
-        const int f = idx / K;
-        const int rem = idx - f * K;
-        const int nx = rem / NZ, iz = rem - nx * NZ;
+    for (int km = 0; km < Cfg::NM; ++km) {
+      const int m = tbase + km * NT;
+      if (m < K) {
+        const int nx = m / NZ, iz = m - nx * NZ;
         const int nz = iz < P ? iz : iz - NZ;
         const int kk = ((nz % PP) + PP) % PP;
         const int tt = (((r * nz) % MZ) + MZ) % MZ;
-        const C term = cmul(Yb[(f * L + nx) * Cfg::YP + kk], rootZ[tt]);
-        if constexpr (kGAcc) {
-          VT* pn = nl + 2 * (((size_t(f) * My + j) * E + e) * K + rem);
-          C v = r > 0 ? cadd(ld2<T>(pn), term) : term;
-          if (r == R - 1) v = cscale(v, inv);
-          st2<T>(pn, v);
-        } else {
-          acc[k] = cadd(acc[k], term);
+        const C w = rootZ[tt];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const C term = cmul(Yb[(f * L + nx) * Cfg::YP + kk], w);
+          if constexpr (kGAcc) {
+            VT* pn = nl + 2 * (((size_t(f) * My + j) * E + e) * K + m);
+            C v = r > 0 ? cadd(ld2<T>(pn), term) : term;
+            if (r == R - 1) v = cscale(v, inv);
+            st2<T>(pn, v);
+          } else {
+            acc[f * Cfg::NM + km] = cadd(acc[f * Cfg::NM + km], term);
+          }
         }
       }
     }
@@ -462,14 +466,17 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
   }
 
   // ---- truncated advection spectrum ----------------------------------------------
+  if constexpr (!kGAcc) {
 #pragma unroll
-  for (int k = 0; k < NACC; ++k) {
-    const int idx = tid + k * NT;
-    if (!kGAcc && idx < 3 * K) {
-      const int f = idx / K;
-      const int m = idx - f * K;
-      const size_t off = ((size_t(f) * My + j) * E + e) * K + m;
-      st2<T>(nl + 2 * off, cscale(acc[k], inv));
+    for (int km = 0; km < Cfg::NM; ++km) {
+      const int m = tid + km * NT;
+      if (m < K) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const size_t off = ((size_t(f) * My + j) * E + e) * K + m;
+          st2<T>(nl + 2 * off, cscale(acc[f * Cfg::NM + km], inv));
+        }
+      }
     }
   }
   // ---- plane means: per-wavefront sums added in wavefront order ----------------
