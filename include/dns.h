@@ -76,11 +76,11 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
 /* Several ensembles advanced together (Sec. 3.2 batches members of one
  * configuration; here independent configurations -- different Re, grid, box,
  * dt or flow -- share one dns_step).  Each group is a full ensemble as made by
- * dns_create, with its own operators and buffers.  By default each group's
- * step runs on a stream of its own, forked from and joined back into the
- * grouped handle's stream; DNS_OPT_GROUP_STREAMS = 0 instead runs, at each
- * sub-step, the groups' advection kernels on their own streams and then one
- * per-mode launch over every group.  Grouped steps run eagerly: DNS_OPT_GRAPH = 1 on a grouped
+ * dns_create, with its own operators and buffers.  Each sub-step runs the
+ * groups' advection kernels on streams of their own (forked from and joined
+ * back into the grouped handle's stream) and then one per-mode launch over
+ * every group (DNS_OPT_GROUP_STREAMS selects per-group streams for the whole
+ * step instead).  Grouped steps run eagerly: DNS_OPT_GRAPH = 1 on a grouped
  * handle returns DNS_E_UNSUPPORTED.  Members are numbered group-major: group g
  * holds members [sum of earlier groups' members, + members).
  *   groups  : ngroups descriptions, 1 <= ngroups <= DNS_MAX_GROUPS; read only
@@ -131,7 +131,7 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  into the handle's stream, so that one chain's
                                  advection kernel overlaps another's per-mode
                                  kernel.  Results do not depend on it.  Default:
-                                 2 for ensembles of 8 or more members, else 1. */
+                                 1.                                             */
 #define DNS_OPT_ADVECTION 8   /* value: DNS_ADV_*, the form of the advection term;
                                  DNS_E_UNSUPPORTED if no variant of that form is
                                  built for the grid at the current precision   */
@@ -164,14 +164,14 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  Default 0.                                     */
 #define DNS_OPT_V_DISCRETIZATION 12 /* value: DNS_VDISC_*; rebuilds the v operators
                                  on the host (long double) and reloads them   */
-#define DNS_OPT_GROUP_STREAMS 13 /* grouped handles only.  value 1 (default):
-                                 each group's whole step runs on a stream of
-                                 its own; 0: each sub-step runs every group's
-                                 per-mode work (right-hand sides, solves,
-                                 velocities) in one launch, a descriptor per
-                                 group, after the groups' advection kernels ran
-                                 on their own streams (1 is used anyway while a
-                                 group has an external forcing or the groups'
+#define DNS_OPT_GROUP_STREAMS 13 /* grouped handles only.  value 0 (default):
+                                 each sub-step runs every group's per-mode work
+                                 (right-hand sides, solves, velocities) in one
+                                 launch, a descriptor per group, after the
+                                 groups' advection kernels ran on their own
+                                 streams; 1: each group's whole step runs on a
+                                 stream of its own (used anyway while a group
+                                 has an external forcing or the groups'
                                  precisions differ).  Results do not depend on
                                  it.                                            */
 

@@ -97,11 +97,11 @@ struct dns_handle {
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   dns_handle* parent = nullptr;
-  // grouped handle: group_streams = true (the default) runs each group's
-  // kernels on its own stream; false runs every group's per-mode work in one
-  // launch per sub-step (descriptors [sub-step][group] and block offsets on the
-  // device, their host copy to detect changes)
-  bool group_streams = true;
+  // grouped handle: every group's per-mode work in one launch per sub-step
+  // (descriptors [sub-step][group] and block offsets on the device, their host
+  // copy to detect changes); group_streams = true runs each group's kernels on
+  // its own stream instead
+  bool group_streams = false;
   ModeArgs* gdesc = nullptr;
   int* gfirst = nullptr;
   std::vector<ModeArgs> gdesc_host;
@@ -942,8 +942,9 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
   // kernel's first launch
   if (plane_preload(Nx, Nz) != hipSuccess || mode_preload() != hipSuccess || misc_preload() != hipSuccess)
     return fail_free(DNS_E_HIP, "resolving kernels");
-  // two member chains overlap the advection and per-mode kernels of a step
-  if (set_chains(h, h->E >= 8 ? 2 : 1) != DNS_OK) return fail_free(DNS_E_HIP, "creating chain streams");
+  // one member chain: every launch of a step covers the whole ensemble
+  // (DNS_OPT_CHAINS splits it so that chains overlap each other's kernels)
+  if (set_chains(h, 1) != DNS_OK) return fail_free(DNS_E_HIP, "creating chain streams");
 
   auto up = [&](double* dst, const std::vector<double>& src) {
     return hipMemcpy(dst, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice);

@@ -312,10 +312,13 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
         }
         const C x0 = C{p.x - nz0 * q.y, nz0 * p.y + q.x};            // p + i q
         const C x2 = C{nz0 * (p2.x + q2.y), nz0 * (q2.x - p2.y)};    // conj(p2) + i conj(q2)
-        // radix 3 with a zero middle input: Y[n1] = x0 + w3^{2 n1} x2
+        // radix 3 with a zero middle input: Y[n1] = x0 + w3^{2 n1} x2, with
+        // w3^{2}, w3^{4} = c3 -/+ i s3 sharing x0 + c3 x2 and s3 x2
         v[0] = cadd(x0, x2);
-        v[1] = cmul(cadd(x0, cmul(x2, C{c3, -s3})), tw1);
-        v[2] = cmul(cadd(x0, cmul(x2, C{c3, s3})), tw2);
+        const C m{x0.x + c3 * x2.x, x0.y + c3 * x2.y};
+        const T sx = s3 * x2.x, sy = s3 * x2.y;
+        v[1] = cmul(C{m.x + sy, m.y - sx}, tw1);
+        v[2] = cmul(C{m.x - sy, m.y + sx}, tw2);
         stages_inv<T, L, 0>(v, stw, ssg);
       };
       // forward transform of this lane's 3 points; kept modes kx = lane and
@@ -324,7 +327,9 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
         stages_fwd<T, L, LOGL - 1>(v, stw, ssg);
         const C y0 = v[0], y1 = cmul(v[1], cconj(tw1)), y2 = cmul(v[2], cconj(tw2));
         const C o0 = cadd(cadd(y0, y1), y2);
-        const C o2 = cadd(y0, cadd(cmul(y1, C{c3, s3}), cmul(y2, C{c3, -s3})));
+        // y1 w3 + y2 w3^{-1} = c3 (y1 + y2) + i s3 (y1 - y2)
+        const C sp = cadd(y1, y2), dm = csub(y1, y2);
+        const C o2{y0.x + c3 * sp.x - s3 * dm.y, y0.y + c3 * sp.y + s3 * dm.x};
         C* row = zf + (f * PH + qp) * Cfg::FP;
         row[lane] = o0;
         row[L + lane] = o2;

@@ -2,9 +2,9 @@
 
 The grouped workload holds three Couette groups of different Re and grid
 (16x33x16 / 32x49x32 / 48x65x48; 64 / 40 / 24 members).  By default each
-group's kernels run on a stream of its own; DNS_OPT_GROUP_STREAMS = 0 runs,
-at each sub-step, every group's per-mode work in one launch (a descriptor per
-group) instead.  Either way a grouped run must equal, bit for bit, the groups run
+sub-step runs every group's per-mode work in one launch (a descriptor per
+group); DNS_OPT_GROUP_STREAMS = 1 runs each group's kernels on a stream of its
+own instead.  Either way a grouped run must equal, bit for bit, the groups run
 one at a time; the 48x65x48 grid (not used by the other workloads) is also
 checked against the oracle, on sampled members.
 """
