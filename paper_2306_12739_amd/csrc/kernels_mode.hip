@@ -66,7 +66,7 @@ template <class Store>
 __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int RT, int KT,
                                               const double* X, int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = lane >> 4;
   for (int t = wave; t < RT * CT; t += kWaves) {
     const int rt = t / CT, ct = t - rt * CT;
@@ -197,7 +197,7 @@ __device__ __forceinline__ bool mfma_jobs_fit(const CJob (&job)[NJ], int CT) {
 template <bool kDefer, int NJ, class Store>
 __device__ __forceinline__ void mfma_jobs(const CJob (&job)[NJ], int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = lane >> 4;
   int base[NJ + 1];
   base[0] = 0;
@@ -286,7 +286,7 @@ __device__ __forceinline__ void mfma_contract_split(const unsigned short* __rest
                                                     const unsigned short* __restrict__ Lo, int RT, int KT,
                                                     const double* X, int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = (lane >> 4) * 4;
   for (int t = wave; t < RT * CT; t += kWaves) {
     const int rt = t / CT, ct = t - rt * CT;
@@ -321,7 +321,7 @@ template <class Store>
 __device__ __forceinline__ void mfma_contract_f32(const float* __restrict__ Mt, int RT, int KT, const double* X,
                                                   int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = lane >> 4;
   for (int t = wave; t < RT * CT; t += kWaves) {
     const int rt = t / CT, ct = t - rt * CT;
