@@ -124,7 +124,10 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  the lane-parallel x-transform kernel, which is
                                  the default there                              */
 #define DNS_OPT_MODE_TILE 6   /* value: members per workgroup of the per-mode kernel,
-                                 1, 2, 4 or 8, fitting 160 KB of LDS           */
+                                 1, 2, 4 or 8, fitting 160 KB of LDS; the tile
+                                 runs in workgroups of 512 threads when two fit
+                                 a CU, else of 1024 when one does.  Default: the
+                                 largest tile giving sixteen waves per CU      */
 #define DNS_OPT_CHAINS 7      /* value: 1..DNS_MAX_CHAINS (<= ensemble): the members
                                  are advanced in this many contiguous chains, each
                                  on a stream of its own forked from and joined

@@ -64,6 +64,7 @@ struct dns_handle {
   double* staging = nullptr;
   size_t staging_bytes = 0;
   int ET = 1, ntiles = 1;
+  int mode_threads = kModeThreadsNarrow;  // per-mode workgroup size of tile ET (mode_tile_threads)
   int plane_var[2][kPlaneForms] = {};  // plane-kernel variant per precision (FP64, mixed) and form
   int advection = DNS_ADV_ADVECTIVE;
   // shared-mean ensemble: one streamwise mean for all members, optionally
@@ -256,6 +257,7 @@ ModeArgs mode_args(dns_handle* h, int stage, int e0 = 0, int ec = -1) {
   a.CRP = h->CRP;
   a.SR = h->SR;
   a.TR = h->TR;
+  a.threads = h->mode_threads;
   a.gamma = h->gamma;
   a.failed = h->failed;
   a.divmax = h->divmax;
@@ -354,18 +356,20 @@ hipError_t plane_launch(dns_handle* h, bool sums, int e0 = 0, int ec = -1, hipSt
 }
 
 // Members per mode-kernel workgroup: 1, 2, 4 or 8, at most the ensemble size
-// (rounded up to a power of two) and within 160 KB of LDS.
+// (rounded up to a power of two) and within 160 KB of LDS at the workgroup size
+// the tile uses.
 bool mode_tile_ok(const dns_handle* h, int et) {
   if (et != 1 && et != 2 && et != 4 && et != 8) return false;
   if (et > 1 && et / 2 >= h->E) return false;
   int crp, sr, tr;
   mode_lds_geometry(h->My, et, &crp, &sr, &tr);
-  return size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds <= kLdsPerCU;
+  return size_t(2 * sr + tr) * crp * sizeof(double) + mode_static_lds(mode_tile_threads(h->My, et)) <= kLdsPerCU;
 }
 
 void set_mode_tile(dns_handle* h, int et) {
   h->ET = et;
   h->ntiles = (h->E + et - 1) / et;
+  h->mode_threads = mode_tile_threads(h->My, et);
   mode_lds_geometry(h->My, et, &h->CRP, &h->SR, &h->TR);
 }
 
@@ -523,9 +527,26 @@ int update_group_descs(dns_handle* h) {
       dns_handle* sh = h->sub[g];
       int e0, ec;
       chain_slice(sh, c, nc, &e0, &ec);
-      for (int st = 0; st < 3; ++st) d[(size_t(c) * 3 + st) * ng + g] = mode_args(sh, st, e0, ec);
-      fc[g + 1] = fc[g] + sh->G * ((ec + sh->ET - 1) / sh->ET);
-      lds = std::max(lds, size_t(2 * sh->SR + sh->TR) * sh->CRP * sizeof(double));
+      // the shared launch runs 512-thread workgroups: a group whose own tile
+      // needs 1024 threads takes the largest tile of two such workgroups per CU
+      // (results do not depend on the tile)
+      int et = sh->ET, crp = sh->CRP, sr = sh->SR, tr = sh->TR;
+      if (sh->mode_threads != kModeThreadsNarrow) {
+        et = mode_member_tile(sh->My, sh->E, true);
+        mode_lds_geometry(sh->My, et, &crp, &sr, &tr);
+      }
+      for (int st = 0; st < 3; ++st) {
+        ModeArgs a = mode_args(sh, st, e0, ec);
+        a.ET = et;
+        a.ntiles = (ec + et - 1) / et;
+        a.CRP = crp;
+        a.SR = sr;
+        a.TR = tr;
+        a.threads = kModeThreadsNarrow;
+        d[(size_t(c) * 3 + st) * ng + g] = a;
+      }
+      fc[g + 1] = fc[g] + sh->G * ((ec + et - 1) / et);
+      lds = std::max(lds, size_t(2 * sr + tr) * crp * sizeof(double));
     }
   }
   const bool same = h->gdesc_host.size() == d.size() &&
@@ -786,7 +807,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     // one member per per-mode workgroup must fit the workgroup LDS (Ny <= 254)
     int crp, sr, tr;
     mode_lds_geometry(Ny, 1, &crp, &sr, &tr);
-    if (size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds > kLdsPerCU)
+    if (size_t(2 * sr + tr) * crp * sizeof(double) + mode_static_lds(kModeThreadsNarrow) > kLdsPerCU)
       return fail(nullptr, DNS_E_UNSUPPORTED, "Ny too large: the per-mode kernel's LDS holds Ny <= 254");
   }
 
@@ -815,7 +836,7 @@ int dns_create(const dns_geometry* g, double Re, int Nx, int Ny, int Nz, int ens
     h->Ubot = -h->Uw;
     h->Utop = h->Uw;
   }
-  set_mode_tile(h, mode_member_tile(h->My, h->E));
+  set_mode_tile(h, mode_member_tile(h->My, h->E, false));
 
   HostOperators ho;
   if (build_operators(h->My, h->L, h->P, h->kxs, h->kzs, Re, dt, h->Ubot, h->Utop, &ho) != 0) {

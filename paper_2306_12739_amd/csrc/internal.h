@@ -86,6 +86,7 @@ struct ModeArgs {
   int My, N, K, E, L, P, NZ, G, ET, ntiles;
   int e0, ec;           // members [e0, e0 + ec) of this launch (ntiles covers ec)
   int CRP, SR, TR;      // LDS geometry (mode_lds_geometry)
+  int threads;          // workgroup size of launch_mode: 512 or 1024 (mode_tile_threads)
   double kxs, kzs, hdt, Ubot, Utop, Qtarget;
   int stage;      // 0, 1, 2: sub-step index; -1: velocities of the state only
   int freeze_mean;  // 1: sub-steps leave the n_x = 0 modes and U, W untouched
@@ -123,13 +124,15 @@ hipError_t launch_mode_grouped(int precision, bool forced, const ModeArgs* descs
 hipError_t plane_preload(int Nx, int Nz);
 hipError_t mode_preload();
 hipError_t misc_preload();
-int mode_member_tile(int My, int E);
+int mode_member_tile(int My, int E, bool narrow_only);
 void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR);
-// per-mode workgroup: threads, and its static LDS (per-wave reduction slots of
-// up to 16 columns, per-member gamma); LDS of one CU
-constexpr int kModeThreads = 512;
-constexpr size_t kModeStaticLds = (kModeThreads / 64 * 16 + 64) * sizeof(double);
+// per-mode workgroup sizes (512 threads; 1024 for member tiles whose LDS fits
+// one workgroup per CU), the static LDS of a workgroup of that size (per-wave
+// reduction slots of up to 16 columns, per-member gamma); LDS of one CU
+constexpr int kModeThreadsNarrow = 512, kModeThreadsWide = 1024;
+constexpr size_t mode_static_lds(int threads) { return size_t(threads / 64 * 16 + 64) * sizeof(double); }
 constexpr size_t kLdsPerCU = 160 * 1024;
+int mode_tile_threads(int My, int ET);
 
 // Row-major R x Kd matrix -> bfloat16 A-operand tiles of the 16x16x16 BF16 MFMA,
 // split M = hi + lo (each rounded to nearest even): tile (rt, kt), kt <

@@ -51,9 +51,11 @@ __device__ __forceinline__ int xcd_logical_m(int b, int nblk) {
   return (x < rem ? x * (q + 1) : rem * (q + 1) + (x - rem) * q) + local;
 }
 
-constexpr int kNT = kModeThreads;
-constexpr int kWaves = kNT / 64;
-static_assert(kModeStaticLds == (kWaves * 16 + 64) * sizeof(double), "static LDS of mode_body");
+// The workgroup size NT (512 or 1024 threads: kModeThreadsNarrow, kModeThreadsWide) is a
+// template parameter of the kernel and of every helper below; NT / 64 waves.
+static_assert(mode_static_lds(kModeThreadsNarrow) == (kModeThreadsNarrow / 64 * 16 + 64) * sizeof(double) &&
+                  mode_static_lds(kModeThreadsWide) == (kModeThreadsWide / 64 * 16 + 64) * sizeof(double),
+              "static LDS of mode_body");
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -62,13 +64,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // padding rows).  M: tiled matrix with K = 4 KT columns (zero padded),
 // X: LDS, row stride ldx, at least 4 KT finite rows.
 // D layout of v_mfma_f64_16x16x4f64: lane l, register r -> row l/16 + 4r, col l%16.
-template <class Store>
+template <int NT, class Store>
 __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int RT, int KT,
                                               const double* X, int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = lane >> 4;
-  for (int t = wave; t < RT * CT; t += kWaves) {
+  for (int t = wave; t < RT * CT; t += (NT / 64)) {
     const int rt = t / CT, ct = t - rt * CT;
     const double* a = Mt + size_t(rt) * KT * 64 + lane;
     const double* b = X + lk * ldx + ct * 16 + lr;
@@ -180,21 +182,21 @@ __device__ __forceinline__ void mfma_tile_pair(const CJob J1, int rt1, int ct1, 
 
 // Every output tile of NJ jobs that share the column tiling (CT) and the
 // operand row stride ldx: tiles are numbered job-major and wave w takes tiles
-// w, w + kWaves, ... two at a time.  store(job, row, col, value) as in
+// w, w + (waves), ... two at a time.  store(job, row, col, value) as in
 // mfma_contract.  kDefer: every wave first computes all its tiles (at most
 // kMaxHeld) into registers, the workgroup synchronises, then the stores run,
 // so a job may overwrite any job's operand; the caller checks the tile count
 // (mfma_jobs_fit).
 constexpr int kMaxHeld = 4;
-template <int NJ>
+template <int NT, int NJ>
 __device__ __forceinline__ bool mfma_jobs_fit(const CJob (&job)[NJ], int CT) {
   int total = 0;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) total += job[j].RT * CT;
-  return total <= kMaxHeld * kWaves;
+  return total <= kMaxHeld * (NT / 64);
 }
 
-template <bool kDefer, int NJ, class Store>
+template <int NT, bool kDefer, int NJ, class Store>
 __device__ __forceinline__ void mfma_jobs(const CJob (&job)[NJ], int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
@@ -234,7 +236,7 @@ __device__ __forceinline__ void mfma_jobs(const CJob (&job)[NJ], int ldx, int CT
     d4 held[kMaxHeld];
 #pragma unroll
     for (int i = 0; i < kMaxHeld; i += 2) {
-      const int t1 = wave + i * kWaves, t2 = t1 + kWaves;
+      const int t1 = wave + i * (NT / 64), t2 = t1 + (NT / 64);
       if (t1 < total) {
         CJob J1, J2 = job[0];
         int j1, rt1, ct1, j2 = 0, rt2 = 0, ct2 = 0;
@@ -246,12 +248,12 @@ __device__ __forceinline__ void mfma_jobs(const CJob (&job)[NJ], int ldx, int CT
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kMaxHeld; ++i) {
-      const int t = wave + i * kWaves;
+      const int t = wave + i * (NT / 64);
       if (t < total) put(t, held[i]);
     }
   } else {
-    for (int t1 = wave; t1 < total; t1 += 2 * kWaves) {
-      const int t2 = t1 + kWaves;
+    for (int t1 = wave; t1 < total; t1 += 2 * (NT / 64)) {
+      const int t2 = t1 + (NT / 64);
       CJob J1, J2 = job[0];
       int j1, rt1, ct1, j2 = 0, rt2 = 0, ct2 = 0;
       decode(t1, &J1, &j1, &rt1, &ct1);
@@ -281,14 +283,14 @@ __device__ __forceinline__ float bf16_value(short h) {
 // M X ~ Mhi Xhi + Mhi Xlo + Mlo Xhi on v_mfma_f32_16x16x16bf16_1k with FP32
 // accumulation (the Mlo Xlo term is below FP32 resolution).  X needs 16 KT
 // finite rows.  D layout: lane l, register r -> row 4 (l / 16) + r, col l % 16.
-template <class Store>
+template <int NT, class Store>
 __device__ __forceinline__ void mfma_contract_split(const unsigned short* __restrict__ Hi,
                                                     const unsigned short* __restrict__ Lo, int RT, int KT,
                                                     const double* X, int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = (lane >> 4) * 4;
-  for (int t = wave; t < RT * CT; t += kWaves) {
+  for (int t = wave; t < RT * CT; t += (NT / 64)) {
     const int rt = t / CT, ct = t - rt * CT;
     const bf16x4* ah = reinterpret_cast<const bf16x4*>(Hi) + size_t(rt) * KT * 64 + lane;
     const bf16x4* al = reinterpret_cast<const bf16x4*>(Lo) + size_t(rt) * KT * 64 + lane;
@@ -317,13 +319,13 @@ __device__ __forceinline__ void mfma_contract_split(const unsigned short* __rest
 // tiles (K = 4 KT), X rounded to FP32, FP32 accumulation on
 // v_mfma_f32_16x16x4f32.  D layout: lane l, register r -> row 4 (l / 16) + r,
 // col l % 16.
-template <class Store>
+template <int NT, class Store>
 __device__ __forceinline__ void mfma_contract_f32(const float* __restrict__ Mt, int RT, int KT, const double* X,
                                                   int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = lane >> 4;
-  for (int t = wave; t < RT * CT; t += kWaves) {
+  for (int t = wave; t < RT * CT; t += (NT / 64)) {
     const int rt = t / CT, ct = t - rt * CT;
     const float* a = Mt + size_t(rt) * KT * 64 + lane;
     const double* b = X + lk * ldx + ct * 16 + lr;
@@ -351,15 +353,15 @@ constexpr int kDerFP64 = 0, kDerSplitBF16 = 1, kDerFP32 = 2;
 
 // A y-derivative contraction (one of the six parity halves, index `which`).
 // Kd is the K dimension.
-template <int kDer, class Store>
+template <int kDer, int NT, class Store>
 __device__ __forceinline__ void dcontract(const ModeArgs& a, int which, const double* Mt, int RT, int Kd,
                                           const double* X, int ldx, int CT, Store store) {
   if constexpr (kDer == kDerSplitBF16)
-    mfma_contract_split(a.Dhi[which], a.Dlo[which], RT, (Kd + 15) / 16, X, ldx, CT, store);
+    mfma_contract_split<NT>(a.Dhi[which], a.Dlo[which], RT, (Kd + 15) / 16, X, ldx, CT, store);
   else if constexpr (kDer == kDerFP32)
-    mfma_contract_f32(a.Df[which], RT, (Kd + 3) / 4, X, ldx, CT, store);
+    mfma_contract_f32<NT>(a.Df[which], RT, (Kd + 3) / 4, X, ldx, CT, store);
   else
-    mfma_contract(Mt, RT, (Kd + 3) / 4, X, ldx, CT, store);
+    mfma_contract<NT>(Mt, RT, (Kd + 3) / 4, X, ldx, CT, store);
 }
 
 template <typename VT>
@@ -390,7 +392,7 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 //   T  : Q = i kx N_u + i kz N_w (FH), later v (FH), later du/dy (FH)
 // The per-mode work of workgroup `flat` (a group and member tile) of the
 // launch described by `a`.
-template <typename VT, int kDer, bool kForce>
+template <typename VT, int kDer, bool kForce, int NT>
 __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
@@ -403,7 +405,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   double* S = smem;
   double* S2 = S + size_t(SR) * CRP;
   double* T = S2 + size_t(SR) * CRP;
-  __shared__ double red[kWaves * 16];  // per-wave maxima of <= 16 columns
+  __shared__ double red[(NT / 64) * 16];  // per-wave maxima of <= 16 columns
   __shared__ double gam_s[64];
 
   const int g = flat / a.ntiles;
@@ -436,7 +438,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   const double kx = a.kxs * nx;
 
   // zero all buffers once (padding rows and columns must hold finite zeros)
-  for (int q = tid; q < (2 * SR + TR) * CRP; q += kNT) smem[q] = 0.0;
+  for (int q = tid; q < (2 * SR + TR) * CRP; q += NT) smem[q] = 0.0;
   __syncthreads();
 
   // tile counts of the half-size matrices
@@ -512,25 +514,25 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           }
         }
       };
-      for (int q = tid; q < Fe * C; q += 2 * kNT) {
+      for (int q = tid; q < Fe * C; q += 2 * NT) {
         P2 a1[3], a2[3], b1[3], b2[3];
         const bool oka = nl_load(q, a1, a2);
-        const bool okb = nl_load(q + kNT, b1, b2);
+        const bool okb = nl_load(q + NT, b1, b2);
         if (oka) nl_item(q, a1, a2);
-        if (okb) nl_item(q + kNT, b1, b2);
+        if (okb) nl_item(q + NT, b1, b2);
       }
       __syncthreads();
       // F = -k^2 N_v - D1 Q: odd F from even Q, even F from odd Q
       if constexpr (kDer != kDerFP64) {
-        dcontract<kDer>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+        dcontract<kDer, NT>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
         });
-        dcontract<kDer>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        dcontract<kDer, NT>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
           if (r < He) S[(He + r) * CRP + cc] -= v;
         });
       } else {
         const CJob jf[2] = {{a.D1intT_e, RTo, (Fe + 3) / 4, T}, {a.D1intT_o, RTe, (Fo + 3) / 4, T + size_t(Fe) * CRP}};
-        mfma_jobs<false>(jf, CRP, CT, [&](int j, int r, int cc, double v) {
+        mfma_jobs<NT, false>(jf, CRP, CT, [&](int j, int r, int cc, double v) {
           if (j == 0) {
             if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
           } else if (r < He) {
@@ -618,17 +620,17 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         S2[rowX * CRP + 2 * c] = 0.5 * (e1.x + sg * e2.x);
         S2[rowX * CRP + 2 * c + 1] = 0.5 * (e1.y + sg * e2.y);
       };
-      for (int q = tid; q < N * C; q += 2 * kNT) {
+      for (int q = tid; q < N * C; q += 2 * NT) {
         RkIn ia, ib;
         rk_load(q, ia);
-        rk_load(q + kNT, ib);
+        rk_load(q + NT, ib);
         ia.hf = ib.hf = ia.hg = ib.hg = double2{0.0, 0.0};
         if (s > 0) {
           rk_load_hist(q, ia);
-          rk_load_hist(q + kNT, ib);
+          rk_load_hist(q + NT, ib);
         }
         if (ia.ok) rk_item(q, ia);
-        if (ib.ok) rk_item(q + kNT, ib);
+        if (ib.ok) rk_item(q + NT, ib);
       }
       __syncthreads();
       const double* opve = a.opsT + size_t(g) * a.op_group_stride;
@@ -639,37 +641,37 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       // eta halves -> S (FH); rows beyond My keep finite stack data that only
       // meets zero padding columns of D1.  Both solves in one pass when every
       // wave can hold its tiles until the v stack in S has been read.
-      for (int q = tid; q < CRP; q += kNT) {
+      for (int q = tid; q < CRP; q += NT) {
         T[q] = 0.0;
         T[Fe * CRP + q] = 0.0;
       }
       const CJob js[4] = {{opve, RTe, KSe, S}, {opvo, RTo, KSo, S + size_t(2 * He) * CRP},
                           {opee, RTe, KSe, S2}, {opeo, RTo, KSo, S2 + size_t(2 * He) * CRP}};
-      if (mfma_jobs_fit(js, CT)) {
-        mfma_jobs<true>(js, CRP, CT, [&](int j, int r, int cc, double v) {
+      if (mfma_jobs_fit<NT>(js, CT)) {
+        mfma_jobs<NT, true>(js, CRP, CT, [&](int j, int r, int cc, double v) {
           const int lim = (j & 1) ? Ho : He;
           if (r < lim) ((j < 2) ? T : S)[((j & 1) ? Fe + 1 + r : 1 + r) * CRP + cc] = v;
         });
-        for (int q = tid; q < CRP; q += kNT) {
+        for (int q = tid; q < CRP; q += NT) {
           S[q] = 0.0;
           S[Fe * CRP + q] = 0.0;
         }
       } else {
-        mfma_contract(opve, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opve, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
           if (r < He) T[(1 + r) * CRP + cc] = v;
         });
-        mfma_contract(opvo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opvo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
         });
         __syncthreads();
-        for (int q = tid; q < CRP; q += kNT) {
+        for (int q = tid; q < CRP; q += NT) {
           S[q] = 0.0;
           S[Fe * CRP + q] = 0.0;
         }
-        mfma_contract(opee, RTe, KSe, S2, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opee, RTe, KSe, S2, CRP, CT, [&](int r, int cc, double v) {
           if (r < He) S[(1 + r) * CRP + cc] = v;
         });
-        mfma_contract(opeo, RTo, KSo, S2 + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opeo, RTo, KSo, S2 + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) S[(Fe + 1 + r) * CRP + cc] = v;
         });
       }
@@ -678,7 +680,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         // Hermitian projection of the n_x = 0 column: (0, nz) and (0, -nz);
         // a per-node combination of two columns, so it acts on halves as is
         if (nx == 0 && az > 0) {
-          for (int q = tid; q < My * ET; q += kNT) {
+          for (int q = tid; q < My * ET; q += NT) {
             const int i = q >> ets, c0 = q & (ET - 1), c1 = c0 + ET;
 #pragma unroll
             for (int bsel = 0; bsel < 2; ++bsel) {
@@ -695,7 +697,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           __syncthreads();
         }
         // state: interior node pairs (kk, N-1-kk) from FH rows 1 + kk, Fe + 1 + kk
-        for (int q = tid; q < He * C; q += kNT) {
+        for (int q = tid; q < He * C; q += NT) {
           const int kk = q >> cs, c = q & (C - 1);
           if (!col_valid(c)) continue;
           const int re = 1 + kk, ro = Fe + 1 + kk;
@@ -730,7 +732,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
     } else {
       // velocities of the stored state: v -> T (FH), eta -> S (FH)
-      for (int q = tid; q < He * C; q += kNT) {
+      for (int q = tid; q < He * C; q += NT) {
         const int kk = q >> cs, c = q & (C - 1);
         if (!col_valid(c)) continue;
         const size_t s1 = st(kk, c);
@@ -756,15 +758,15 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     __syncthreads();
     // ---- velocity recovery: dv/dy = D1c v (odd <- even, even <- odd) -> S2 FH
     if constexpr (kDer != kDerFP64) {
-      dcontract<kDer>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kDer>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) S2[r * CRP + cc] = v;
       });
     } else {
       const CJob jc[2] = {{a.D1cT_e, RFo, (He + 3) / 4, T + CRP}, {a.D1cT_o, RFe, (Ho + 3) / 4, T + size_t(Fe + 1) * CRP}};
-      mfma_jobs<false>(jc, CRP, CT, [&](int j, int r, int cc, double v) {
+      mfma_jobs<NT, false>(jc, CRP, CT, [&](int j, int r, int cc, double v) {
         if (j == 0) {
           if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
         } else if (r < Fe) {
@@ -774,7 +776,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     }
     __syncthreads();
     double dmax = 0.0;
-    for (int q = tid; q < Fe * C; q += kNT) {
+    for (int q = tid; q < Fe * C; q += NT) {
       const int k = q >> cs, c = q & (C - 1);
       const double kz = col_kz(c), k2 = kx * kx + kz * kz;
       const double ik2 = k2 > 0.0 ? 1.0 / k2 : 0.0;
@@ -821,8 +823,8 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
                         {a.D1T_e, RFo, (Fe + 3) / 4, S}, {a.D1T_o, RFe, (Fo + 3) / 4, S + size_t(Fe) * CRP}};
     bool merged = false;
     if constexpr (kDer == kDerFP64) {
-      if (mfma_jobs_fit(jd, CT)) {
-        mfma_jobs<true>(jd, CRP, CT, [&](int j, int r, int cc, double v) {
+      if (mfma_jobs_fit<NT>(jd, CT)) {
+        mfma_jobs<NT, true>(jd, CRP, CT, [&](int j, int r, int cc, double v) {
           const int lim = (j & 1) ? Fe : Fo;
           if (r < lim) ((j < 2) ? T : S2)[((j & 1) ? r : Fe + r) * CRP + cc] = v;
         });
@@ -830,22 +832,22 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
     }
     if (!merged) {
-      dcontract<kDer>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) T[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kDer>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) T[r * CRP + cc] = v;
       });
       __syncthreads();
-      dcontract<kDer>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kDer>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) S2[r * CRP + cc] = v;
       });
     }
     __syncthreads();
-    for (int q = tid; q < Fe * C; q += kNT) {
+    for (int q = tid; q < Fe * C; q += NT) {
       const int k = q >> cs, c = q & (C - 1);
       if (!col_valid(c)) continue;
       write_pair(T, k, c, 3);
@@ -860,7 +862,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       __syncthreads();
       if (tid < C && col_valid(tid)) {
         double mx = 0.0;
-        for (int w = 0; w < kWaves; ++w) mx = fmax(mx, red[w * C + tid]);
+        for (int w = 0; w < (NT / 64); ++w) mx = fmax(mx, red[w * C + tid]);
         atomicMax(&a.divmax[col_member(tid)], (unsigned long long)__double_as_longlong(mx));
       }
     }
@@ -873,7 +875,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   const int NM = ET;
   if (s >= 0) {
     // plane means (FH halves)
-    for (int q = tid; q < Fe * NM; q += kNT) {
+    for (int q = tid; q < Fe * NM; q += NT) {
       const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
       if (e >= mend) continue;
       const int j2 = My - 1 - k;
@@ -891,14 +893,14 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     }
     __syncthreads();
     // (E_U, E_W) = -D1 (<uv>, <wv>) on interior halves
-    dcontract<kDer>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kDer, NT>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
       if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] = -v;
     });
-    dcontract<kDer>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kDer, NT>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < He) S[(He + r) * CRP + cc] = -v;
     });
     __syncthreads();
-    for (int q = tid; q < N * NM; q += kNT) {
+    for (int q = tid; q < N * NM; q += NT) {
       const int hr = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
       if (e >= mend) continue;
       const bool even = hr < He;
@@ -934,15 +936,15 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     // (U_a, W) halves = [A_U | B_U] halves -> T (FH)
     const double* me = a.meanT;
     const double* mo = me + size_t(RTe) * KSe * 64;
-    mfma_contract(me, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+    mfma_contract<NT>(me, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
       if (r < He) T[(1 + r) * CRP + cc] = v;
     });
-    mfma_contract(mo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    mfma_contract<NT>(mo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
       if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
     });
     __syncthreads();
     // wall pair, lift on the interior halves
-    for (int q = tid; q < Fe * NM; q += kNT) {
+    for (int q = tid; q < Fe * NM; q += NT) {
       const int k = q >> ets, el = q & (NM - 1);
       if (k == 0) {
         T[2 * el] = 0.5 * (a.Ubot + a.Utop);
@@ -972,13 +974,13 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     }
     __syncthreads();
     // gamma response is even (the green function is symmetric)
-    for (int q = tid; q < He * NM; q += kNT) {
+    for (int q = tid; q < He * NM; q += NT) {
       const int kk = q >> ets, el = q & (NM - 1);
       T[(1 + kk) * CRP + 2 * el] += gam_s[el] * a.green_h[kk];
     }
     __syncthreads();
     if (s == 2) {
-      for (int q = tid; q < Fe * NM; q += kNT) {
+      for (int q = tid; q < Fe * NM; q += NT) {
         const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
         if (e >= mend) continue;
         const double ue = T[k * CRP + 2 * el], we = T[k * CRP + 2 * el + 1];
@@ -1001,7 +1003,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
     }
   } else {
-    for (int q = tid; q < Fe * NM; q += kNT) {
+    for (int q = tid; q < Fe * NM; q += NT) {
       const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
       if (e >= mend) continue;
       const size_t j1 = size_t(k) * E + e, j2 = size_t(My - 1 - k) * E + e;
@@ -1018,14 +1020,14 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   }
   __syncthreads();
   // (0,0) velocity fields: u = U, v = 0, w = W, du/dy = D1 U, dw/dy = D1 W
-  dcontract<kDer>(a, 4, a.D1T_e, RFo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
     if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
   });
-  dcontract<kDer>(a, 5, a.D1T_o, RFe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
     if (r < Fe) S2[r * CRP + cc] = v;
   });
   __syncthreads();
-  for (int q = tid; q < Fe * NM; q += kNT) {
+  for (int q = tid; q < Fe * NM; q += NT) {
     const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
     if (e >= mend) continue;
     const bool pair = k < Fo;
@@ -1046,23 +1048,23 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   }
 }
 
-// Four waves per SIMD (registers <= 128): two workgroups of eight waves per CU
-// when their LDS allows.
-template <typename VT, int kDer, bool kForce>
-__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) mode_kernel(ModeArgs a) {
-  mode_body<VT, kDer, kForce>(a, xcd_logical_m(blockIdx.x, gridDim.x));
+// Four waves per SIMD (registers <= 128): sixteen waves per CU, as two
+// workgroups of 512 threads or one of 1024.
+template <typename VT, int kDer, bool kForce, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) mode_kernel(ModeArgs a) {
+  mode_body<VT, kDer, kForce, NT>(a, xcd_logical_m(blockIdx.x, gridDim.x));
 }
 
 // Several ensembles' per-mode work in one launch (uneven grouped ensembles,
 // members of different Re and grid): workgroups [first[d], first[d + 1]) run
 // descriptor d, each with the launch shape it would have alone.
 template <typename VT, int kDer, bool kForce>
-__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4))) mode_grouped_kernel(const ModeArgs* __restrict__ descs,
+__global__ void __launch_bounds__(kModeThreadsNarrow) __attribute__((amdgpu_waves_per_eu(4))) mode_grouped_kernel(const ModeArgs* __restrict__ descs,
                                                            const int* __restrict__ first, int ndesc) {
   const int b = blockIdx.x;
   int d = 0;
   while (d + 1 < ndesc && b >= first[d + 1]) ++d;
-  mode_body<VT, kDer, kForce>(descs[d], xcd_logical_m(b - first[d], first[d + 1] - first[d]));
+  mode_body<VT, kDer, kForce, kModeThreadsNarrow>(descs[d], xcd_logical_m(b - first[d], first[d + 1] - first[d]));
 }
 
 // LDS geometry of one workgroup; shared with the host launcher.
@@ -1085,14 +1087,29 @@ void mode_lds_geometry(int My, int ET, int* CRP, int* SR, int* TR) {
   *TR = mx(tr, My);
 }
 
-int mode_member_tile(int My, int E) {
-  // largest ET in {1, 2, 4, 8} (<= E) whose LDS allows two workgroups per CU
+// Workgroup size of member tile ET: 512 threads when two workgroups fit a
+// CU's LDS, else 1024 when one does (either way sixteen waves per CU), else 512.
+int mode_tile_threads(int My, int ET) {
+  int crp, sr, tr;
+  mode_lds_geometry(My, ET, &crp, &sr, &tr);
+  const size_t dyn = size_t(2 * sr + tr) * crp * sizeof(double);
+  if (2 * (dyn + mode_static_lds(kModeThreadsNarrow)) <= kLdsPerCU) return kModeThreadsNarrow;
+  if (dyn + mode_static_lds(kModeThreadsWide) <= kLdsPerCU) return kModeThreadsWide;
+  return kModeThreadsNarrow;
+}
+
+// Largest ET in {1, 2, 4, 8} (<= E) whose workgroups give sixteen waves per CU
+// (two of 512 threads, or one of 1024); with narrow_only, whose LDS allows two
+// 512-thread workgroups per CU.
+int mode_member_tile(int My, int E, bool narrow_only) {
   int best = 1;
   for (int et = 1; et <= 8 && et <= E; et *= 2) {
     int crp, sr, tr;
     mode_lds_geometry(My, et, &crp, &sr, &tr);
-    const size_t lds = size_t(2 * sr + tr) * crp * sizeof(double) + kModeStaticLds;
-    if (2 * lds <= kLdsPerCU) best = et;
+    const size_t dyn = size_t(2 * sr + tr) * crp * sizeof(double);
+    const bool two = 2 * (dyn + mode_static_lds(kModeThreadsNarrow)) <= kLdsPerCU;
+    const bool wide = dyn + mode_static_lds(kModeThreadsWide) <= kLdsPerCU;
+    if (two || (wide && !narrow_only)) best = et;
   }
   return best;
 }
@@ -1101,14 +1118,19 @@ namespace {
 // precision 0: FP64 stage buffers; 1: FP32 stage buffers; 2: FP32 stage
 // buffers and split-BF16 derivative products; 3: FP32 stage buffers and FP32
 // matrix-core derivative products
-template <bool kForce>
-const void* mode_fn(int precision) {
+template <bool kForce, int NT>
+const void* mode_fn_t(int precision) {
   switch (precision) {
-    case 0: return reinterpret_cast<const void*>(&mode_kernel<double, kDerFP64, kForce>);
-    case 1: return reinterpret_cast<const void*>(&mode_kernel<float, kDerFP64, kForce>);
-    case 2: return reinterpret_cast<const void*>(&mode_kernel<float, kDerSplitBF16, kForce>);
-    default: return reinterpret_cast<const void*>(&mode_kernel<float, kDerFP32, kForce>);
+    case 0: return reinterpret_cast<const void*>(&mode_kernel<double, kDerFP64, kForce, NT>);
+    case 1: return reinterpret_cast<const void*>(&mode_kernel<float, kDerFP64, kForce, NT>);
+    case 2: return reinterpret_cast<const void*>(&mode_kernel<float, kDerSplitBF16, kForce, NT>);
+    default: return reinterpret_cast<const void*>(&mode_kernel<float, kDerFP32, kForce, NT>);
   }
+}
+template <bool kForce>
+const void* mode_fn(int precision, int threads) {
+  return threads == kModeThreadsWide ? mode_fn_t<kForce, kModeThreadsWide>(precision)
+                                     : mode_fn_t<kForce, kModeThreadsNarrow>(precision);
 }
 template <bool kForce>
 const void* mode_grouped_fn(int precision) {
@@ -1124,8 +1146,9 @@ const void* mode_grouped_fn(int precision) {
 // Resolve the per-mode kernel instantiations on the current device.
 hipError_t mode_preload() {
   for (int prec = 0; prec < 4; ++prec) {
-    for (const void* fn : {mode_fn<false>(prec), mode_fn<true>(prec), mode_grouped_fn<false>(prec),
-                           mode_grouped_fn<true>(prec)}) {
+    for (const void* fn : {mode_fn<false>(prec, kModeThreadsNarrow), mode_fn<true>(prec, kModeThreadsNarrow),
+                           mode_fn<false>(prec, kModeThreadsWide), mode_fn<true>(prec, kModeThreadsWide),
+                           mode_grouped_fn<false>(prec), mode_grouped_fn<true>(prec)}) {
       hipFuncAttributes attr;
       const hipError_t err = hipFuncGetAttributes(&attr, fn);
       if (err != hipSuccess) return err;
@@ -1134,30 +1157,31 @@ hipError_t mode_preload() {
   return hipSuccess;
 }
 
-// The kernel of the precision (as mode_fn); a forcing (a.fv) selects the
-// variant that subtracts it.
+// The kernel of the precision and a.threads (as mode_fn); a forcing (a.fv)
+// selects the variant that subtracts it.
 hipError_t launch_mode(int precision, const ModeArgs& a, hipStream_t s) {
   const int nblk = a.G * a.ntiles;
+  const int threads = a.threads == kModeThreadsWide ? kModeThreadsWide : kModeThreadsNarrow;
   const size_t lds = size_t(2 * a.SR + a.TR) * a.CRP * sizeof(double);
-  const void* fn = a.fv ? mode_fn<true>(precision) : mode_fn<false>(precision);
+  const void* fn = a.fv ? mode_fn<true>(precision, threads) : mode_fn<false>(precision, threads);
   hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (err != hipSuccess) return err;
   void* args[] = {const_cast<ModeArgs*>(&a)};
-  err = hipLaunchKernel(fn, dim3(nblk), dim3(kNT), args, lds, s);
+  err = hipLaunchKernel(fn, dim3(nblk), dim3(threads), args, lds, s);
   return err != hipSuccess ? err : hipGetLastError();
 }
 
 // Every descriptor of descs (device, ndesc entries; first: device, ndesc + 1
-// block offsets) in one launch of nblk workgroups with lds bytes of dynamic
-// LDS (the largest of the descriptors'); forced selects the variant that
-// subtracts an external forcing (each descriptor then needs one).
+// block offsets) in one launch of nblk workgroups of 512 threads with lds bytes
+// of dynamic LDS (the largest of the descriptors'); forced selects the variant
+// that subtracts an external forcing (each descriptor then needs one).
 hipError_t launch_mode_grouped(int precision, bool forced, const ModeArgs* descs, const int* first, int ndesc,
                                int nblk, size_t lds, hipStream_t s) {
   const void* fn = forced ? mode_grouped_fn<true>(precision) : mode_grouped_fn<false>(precision);
   hipError_t err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
   if (err != hipSuccess) return err;
   void* args[] = {const_cast<ModeArgs**>(&descs), const_cast<int**>(&first), &ndesc};
-  err = hipLaunchKernel(fn, dim3(nblk), dim3(kNT), args, lds, s);
+  err = hipLaunchKernel(fn, dim3(nblk), dim3(kModeThreadsNarrow), args, lds, s);
   return err != hipSuccess ? err : hipGetLastError();
 }
 
