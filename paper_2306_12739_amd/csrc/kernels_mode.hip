@@ -59,21 +59,45 @@ static_assert(mode_static_lds(kModeThreadsNarrow) == (kModeThreadsNarrow / 64 * 
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// Dynamic LDS of the per-mode kernel: its work buffers, rows of ld doubles.
+// With 32-double rows the two 16-column halves of every odd row (rows counted
+// from the start of the LDS) trade places.  At a 256-byte row stride two
+// consecutive rows would put the same columns in the same banks, and a
+// matrix-core fragment reads (and its result writes) consecutive rows from the
+// two half-waves of one LDS pass; 16-double rows already put consecutive rows
+// in different banks and stay as they are.
+extern __shared__ double mode_smem[];
+__device__ __forceinline__ int lds_swz_mask(int ld) { return ld == 32 ? 16 : 0; }
+__device__ __forceinline__ int lds_swz(int i, int m) { return i ^ ((i >> 1) & m); }
+// Address of logical element i of the LDS, in a buffer with rows of ld doubles.
+__device__ __forceinline__ const double* lds_at(int i, int ld) { return mode_smem + lds_swz(i, lds_swz_mask(ld)); }
+
+// One work buffer: rows of ld doubles from element off of the dynamic LDS.
+struct LdsBuf {
+  int off, ld, m;
+  __device__ double& operator[](int i) const { return mode_smem[lds_swz(off + i, m)]; }
+  // elements i and i + 1 for even i (the swizzle keeps them adjacent)
+  __device__ double* pair(int i) const { return mode_smem + lds_swz(off + i, m); }
+  // logical element offset of row r, an operand of the contractions (which swizzle)
+  __device__ int row(int r) const { return off + r * ld; }
+};
+
 // Y = M X over every output tile of this workgroup; store(row, col, value) is
 // called once per element with row < 16 RT, col < 16 CT (the caller ignores
 // padding rows).  M: tiled matrix with K = 4 KT columns (zero padded),
-// X: LDS, row stride ldx, at least 4 KT finite rows.
+// X: logical element offset of the first row of an LDS buffer (LdsBuf
+// layout), row stride ldx, at least 4 KT finite rows.
 // D layout of v_mfma_f64_16x16x4f64: lane l, register r -> row l/16 + 4r, col l%16.
 template <int NT, class Store>
 __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int RT, int KT,
-                                              const double* X, int ldx, int CT, Store store) {
+                                              int X, int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = lane >> 4;
   for (int t = wave; t < RT * CT; t += (NT / 64)) {
     const int rt = t / CT, ct = t - rt * CT;
     const double* a = Mt + size_t(rt) * KT * 64 + lane;
-    const double* b = X + lk * ldx + ct * 16 + lr;
+    const double* b = lds_at(X + lk * ldx + ct * 16 + lr, ldx);  // rows lk + 4 kt: one parity
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     int kt = 0;
     for (; kt + 4 <= KT; kt += 4) {
@@ -98,7 +122,7 @@ __device__ __forceinline__ void mfma_contract(const double* __restrict__ Mt, int
 struct CJob {
   const double* Mt;
   int RT, KT;
-  const double* X;
+  int X;  // logical LDS element offset of the operand's first row
 };
 
 // U k-steps of one tile (or of two tiles, interleaved) from k-step kt while
@@ -165,13 +189,13 @@ __device__ __forceinline__ void mfma_tile_pair(const CJob J1, int rt1, int ct1, 
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15, lk = lane >> 4;
   const double* a1 = J1.Mt + size_t(rt1) * J1.KT * 64 + lane;
-  const double* b1 = J1.X + lk * ldx + ct1 * 16 + lr;
+  const double* b1 = lds_at(J1.X + lk * ldx + ct1 * 16 + lr, ldx);
   acc1 = d4{0.0, 0.0, 0.0, 0.0};
   acc2 = d4{0.0, 0.0, 0.0, 0.0};
   int kt = 0;
   if (has2) {
     const double* a2 = J2.Mt + size_t(rt2) * J2.KT * 64 + lane;
-    const double* b2 = J2.X + lk * ldx + ct2 * 16 + lr;
+    const double* b2 = lds_at(J2.X + lk * ldx + ct2 * 16 + lr, ldx);
     const int kc = J1.KT < J2.KT ? J1.KT : J2.KT;
     tile_pair_tail<kKUnroll>(a1, b1, acc1, a2, b2, acc2, ldx, kt, kc);
     int k2 = kt;
@@ -286,7 +310,7 @@ __device__ __forceinline__ float bf16_value(short h) {
 template <int NT, class Store>
 __device__ __forceinline__ void mfma_contract_split(const unsigned short* __restrict__ Hi,
                                                     const unsigned short* __restrict__ Lo, int RT, int KT,
-                                                    const double* X, int ldx, int CT, Store store) {
+                                                    int X, int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
   const int lr = lane & 15, lk = (lane >> 4) * 4;
@@ -294,14 +318,16 @@ __device__ __forceinline__ void mfma_contract_split(const unsigned short* __rest
     const int rt = t / CT, ct = t - rt * CT;
     const bf16x4* ah = reinterpret_cast<const bf16x4*>(Hi) + size_t(rt) * KT * 64 + lane;
     const bf16x4* al = reinterpret_cast<const bf16x4*>(Lo) + size_t(rt) * KT * 64 + lane;
-    const double* b = X + lk * ldx + ct * 16 + lr;
+    // rows lk + q + 16 kt: even q on b0's parity, odd q on b1's
+    const double* b0 = lds_at(X + lk * ldx + ct * 16 + lr, ldx);
+    const double* b1 = lds_at(X + (lk + 1) * ldx + ct * 16 + lr, ldx);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int kt = 0; kt < KT; ++kt) {
       const bf16x4 a_hi = ah[kt * 64], a_lo = al[kt * 64];
       bf16x4 b_hi, b_lo;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float x = float(b[(16 * kt + q) * ldx]);
+        const float x = float((q & 1 ? b1 : b0)[(16 * kt + (q & ~1)) * ldx]);
         const short h = bf16_bits(x);
         b_hi[q] = h;
         b_lo[q] = bf16_bits(x - bf16_value(h));
@@ -320,7 +346,7 @@ __device__ __forceinline__ void mfma_contract_split(const unsigned short* __rest
 // v_mfma_f32_16x16x4f32.  D layout: lane l, register r -> row 4 (l / 16) + r,
 // col l % 16.
 template <int NT, class Store>
-__device__ __forceinline__ void mfma_contract_f32(const float* __restrict__ Mt, int RT, int KT, const double* X,
+__device__ __forceinline__ void mfma_contract_f32(const float* __restrict__ Mt, int RT, int KT, int X,
                                                   int ldx, int CT, Store store) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar tile arithmetic
@@ -328,7 +354,7 @@ __device__ __forceinline__ void mfma_contract_f32(const float* __restrict__ Mt, 
   for (int t = wave; t < RT * CT; t += (NT / 64)) {
     const int rt = t / CT, ct = t - rt * CT;
     const float* a = Mt + size_t(rt) * KT * 64 + lane;
-    const double* b = X + lk * ldx + ct * 16 + lr;
+    const double* b = lds_at(X + lk * ldx + ct * 16 + lr, ldx);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     int kt = 0;
     for (; kt + 4 <= KT; kt += 4) {
@@ -355,7 +381,7 @@ constexpr int kDerFP64 = 0, kDerSplitBF16 = 1, kDerFP32 = 2;
 // Kd is the K dimension.
 template <int kDer, int NT, class Store>
 __device__ __forceinline__ void dcontract(const ModeArgs& a, int which, const double* Mt, int RT, int Kd,
-                                          const double* X, int ldx, int CT, Store store) {
+                                          int X, int ldx, int CT, Store store) {
   if constexpr (kDer == kDerSplitBF16)
     mfma_contract_split<NT>(a.Dhi[which], a.Dlo[which], RT, (Kd + 15) / 16, X, ldx, CT, store);
   else if constexpr (kDer == kDerFP32)
@@ -394,7 +420,6 @@ __device__ __forceinline__ void st_c(VT* p, double re, double im) {
 // launch described by `a`.
 template <typename VT, int kDer, bool kForce, int NT>
 __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
-  extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int My = a.My, N = a.N, K = a.K, E = a.E, NZ = a.NZ, P = a.P, ET = a.ET;
   const int He = (N + 1) / 2, Ho = N / 2, Fe = He + 1, Fo = Ho + 1;
@@ -402,9 +427,8 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   const int CRP = a.CRP;          // real columns, padded to 16
   const int CT = CRP / 16;
   const int SR = a.SR, TR = a.TR;
-  double* S = smem;
-  double* S2 = S + size_t(SR) * CRP;
-  double* T = S2 + size_t(SR) * CRP;
+  const int swm = lds_swz_mask(CRP);
+  const LdsBuf S{0, CRP, swm}, S2{SR * CRP, CRP, swm}, T{2 * SR * CRP, CRP, swm};
   __shared__ double red[(NT / 64) * 16];  // per-wave maxima of <= 16 columns
   __shared__ double gam_s[64];
 
@@ -438,7 +462,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   const double kx = a.kxs * nx;
 
   // zero all buffers once (padding rows and columns must hold finite zeros)
-  for (int q = tid; q < (2 * SR + TR) * CRP; q += NT) smem[q] = 0.0;
+  for (int q = tid; q < (2 * SR + TR) * CRP; q += NT) mode_smem[q] = 0.0;
   __syncthreads();
 
   // tile counts of the half-size matrices
@@ -450,12 +474,12 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   // unconditional so that each stays one vector store: at the centre node of
   // an odd grid (k = Fo, no odd part) both address node k, and the second,
   // in program order, leaves er - 0 = er exactly.
-  auto write_pair = [&](const double* B, int k, int c, int f) {
-    const double er = B[k * CRP + 2 * c], ei = B[k * CRP + 2 * c + 1];
+  auto write_pair = [&](const LdsBuf& B, int k, int c, int f) {
+    const double er = B.pair(k * CRP + 2 * c)[0], ei = B.pair(k * CRP + 2 * c)[1];
     double orr = 0.0, oi = 0.0;
     if (k < Fo) {
-      orr = B[(Fe + k) * CRP + 2 * c];
-      oi = B[(Fe + k) * CRP + 2 * c + 1];
+      orr = B.pair((Fe + k) * CRP + 2 * c)[0];
+      oi = B.pair((Fe + k) * CRP + 2 * c)[1];
     }
     st_c(vel + f * FS + sb(k, c), er + orr, ei + oi);
     st_c(vel + f * FS + sb(My - 1 - k, c), er - orr, ei - oi);
@@ -494,23 +518,23 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           ho[2 * f + 1] = 0.5 * (double(x1[f].y) - double(x2[f].y));
         }
         // Q = i kx N_u + i kz N_w
-        T[k * CRP + 2 * c] = -(kx * he[1] + kz * he[5]);
-        T[k * CRP + 2 * c + 1] = kx * he[0] + kz * he[4];
+        T.pair(k * CRP + 2 * c)[0] = -(kx * he[1] + kz * he[5]);
+        T.pair(k * CRP + 2 * c)[1] = kx * he[0] + kz * he[4];
         if (pair) {
-          T[(Fe + k) * CRP + 2 * c] = -(kx * ho[1] + kz * ho[5]);
-          T[(Fe + k) * CRP + 2 * c + 1] = kx * ho[0] + kz * ho[4];
+          T.pair((Fe + k) * CRP + 2 * c)[0] = -(kx * ho[1] + kz * ho[5]);
+          T.pair((Fe + k) * CRP + 2 * c)[1] = kx * ho[0] + kz * ho[4];
         }
         if (k >= 1) {
           const int kk = k - 1;  // interior half index
-          S[(He + kk) * CRP + 2 * c] = -k2 * he[2];
-          S[(He + kk) * CRP + 2 * c + 1] = -k2 * he[3];
-          S2[(He + kk) * CRP + 2 * c] = -(kz * he[1] - kx * he[5]);
-          S2[(He + kk) * CRP + 2 * c + 1] = kz * he[0] - kx * he[4];
+          S.pair((He + kk) * CRP + 2 * c)[0] = -k2 * he[2];
+          S.pair((He + kk) * CRP + 2 * c)[1] = -k2 * he[3];
+          S2.pair((He + kk) * CRP + 2 * c)[0] = -(kz * he[1] - kx * he[5]);
+          S2.pair((He + kk) * CRP + 2 * c)[1] = kz * he[0] - kx * he[4];
           if (kk < Ho) {
-            S[(2 * He + Ho + kk) * CRP + 2 * c] = -k2 * ho[2];
-            S[(2 * He + Ho + kk) * CRP + 2 * c + 1] = -k2 * ho[3];
-            S2[(2 * He + Ho + kk) * CRP + 2 * c] = -(kz * ho[1] - kx * ho[5]);
-            S2[(2 * He + Ho + kk) * CRP + 2 * c + 1] = kz * ho[0] - kx * ho[4];
+            S.pair((2 * He + Ho + kk) * CRP + 2 * c)[0] = -k2 * ho[2];
+            S.pair((2 * He + Ho + kk) * CRP + 2 * c)[1] = -k2 * ho[3];
+            S2.pair((2 * He + Ho + kk) * CRP + 2 * c)[0] = -(kz * ho[1] - kx * ho[5]);
+            S2.pair((2 * He + Ho + kk) * CRP + 2 * c)[1] = kz * ho[0] - kx * ho[4];
           }
         }
       };
@@ -524,14 +548,14 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       __syncthreads();
       // F = -k^2 N_v - D1 Q: odd F from even Q, even F from odd Q
       if constexpr (kDer != kDerFP64) {
-        dcontract<kDer, NT>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+        dcontract<kDer, NT>(a, 0, a.D1intT_e, RTo, Fe, T.row(0), CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
         });
-        dcontract<kDer, NT>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        dcontract<kDer, NT>(a, 1, a.D1intT_o, RTe, Fo, T.row(Fe), CRP, CT, [&](int r, int cc, double v) {
           if (r < He) S[(He + r) * CRP + cc] -= v;
         });
       } else {
-        const CJob jf[2] = {{a.D1intT_e, RTo, (Fe + 3) / 4, T}, {a.D1intT_o, RTe, (Fo + 3) / 4, T + size_t(Fe) * CRP}};
+        const CJob jf[2] = {{a.D1intT_e, RTo, (Fe + 3) / 4, T.row(0)}, {a.D1intT_o, RTe, (Fo + 3) / 4, T.row(Fe)}};
         mfma_jobs<NT, false>(jf, CRP, CT, [&](int j, int r, int cc, double v) {
           if (j == 0) {
             if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] -= v;
@@ -585,8 +609,8 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         const size_t so = st(hr, c);
         double2* hf = reinterpret_cast<double2*>(a.hF + so);
         double2* hg = reinterpret_cast<double2*>(a.hG + so);
-        double Fr = S[rowF * CRP + 2 * c], Fi = S[rowF * CRP + 2 * c + 1];
-        double Gr = S2[rowF * CRP + 2 * c], Gi = S2[rowF * CRP + 2 * c + 1];
+        double Fr = S.pair(rowF * CRP + 2 * c)[0], Fi = S.pair(rowF * CRP + 2 * c)[1];
+        double Gr = S2.pair(rowF * CRP + 2 * c)[0], Gi = S2.pair(rowF * CRP + 2 * c)[1];
         if constexpr (kForce) {
           // external forcing held over the step enters every sub-step's terms
           // as F - f_lapv, G - f_eta (y-parity halves of the interior values)
@@ -611,14 +635,14 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           Fr = (Hf.x + Fr) * (1.0 / 6.0); Fi = (Hf.y + Fi) * (1.0 / 6.0);
           Gr = (Hg.x + Gr) * (1.0 / 6.0); Gi = (Hg.y + Gi) * (1.0 / 6.0);
         }
-        S[rowF * CRP + 2 * c] = -hdt * Fr;
-        S[rowF * CRP + 2 * c + 1] = -hdt * Fi;
-        S2[rowF * CRP + 2 * c] = -hdt * Gr;
-        S2[rowF * CRP + 2 * c + 1] = -hdt * Gi;
-        S[rowX * CRP + 2 * c] = 0.5 * (v1.x + sg * v2.x);
-        S[rowX * CRP + 2 * c + 1] = 0.5 * (v1.y + sg * v2.y);
-        S2[rowX * CRP + 2 * c] = 0.5 * (e1.x + sg * e2.x);
-        S2[rowX * CRP + 2 * c + 1] = 0.5 * (e1.y + sg * e2.y);
+        S.pair(rowF * CRP + 2 * c)[0] = -hdt * Fr;
+        S.pair(rowF * CRP + 2 * c)[1] = -hdt * Fi;
+        S2.pair(rowF * CRP + 2 * c)[0] = -hdt * Gr;
+        S2.pair(rowF * CRP + 2 * c)[1] = -hdt * Gi;
+        S.pair(rowX * CRP + 2 * c)[0] = 0.5 * (v1.x + sg * v2.x);
+        S.pair(rowX * CRP + 2 * c)[1] = 0.5 * (v1.y + sg * v2.y);
+        S2.pair(rowX * CRP + 2 * c)[0] = 0.5 * (e1.x + sg * e2.x);
+        S2.pair(rowX * CRP + 2 * c)[1] = 0.5 * (e1.y + sg * e2.y);
       };
       for (int q = tid; q < N * C; q += 2 * NT) {
         RkIn ia, ib;
@@ -645,8 +669,8 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         T[q] = 0.0;
         T[Fe * CRP + q] = 0.0;
       }
-      const CJob js[4] = {{opve, RTe, KSe, S}, {opvo, RTo, KSo, S + size_t(2 * He) * CRP},
-                          {opee, RTe, KSe, S2}, {opeo, RTo, KSo, S2 + size_t(2 * He) * CRP}};
+      const CJob js[4] = {{opve, RTe, KSe, S.row(0)}, {opvo, RTo, KSo, S.row(2 * He)},
+                          {opee, RTe, KSe, S2.row(0)}, {opeo, RTo, KSo, S2.row(2 * He)}};
       if (mfma_jobs_fit<NT>(js, CT)) {
         mfma_jobs<NT, true>(js, CRP, CT, [&](int j, int r, int cc, double v) {
           const int lim = (j & 1) ? Ho : He;
@@ -657,10 +681,10 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           S[Fe * CRP + q] = 0.0;
         }
       } else {
-        mfma_contract<NT>(opve, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opve, RTe, KSe, S.row(0), CRP, CT, [&](int r, int cc, double v) {
           if (r < He) T[(1 + r) * CRP + cc] = v;
         });
-        mfma_contract<NT>(opvo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opvo, RTo, KSo, S.row(2 * He), CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
         });
         __syncthreads();
@@ -668,10 +692,10 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           S[q] = 0.0;
           S[Fe * CRP + q] = 0.0;
         }
-        mfma_contract<NT>(opee, RTe, KSe, S2, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opee, RTe, KSe, S2.row(0), CRP, CT, [&](int r, int cc, double v) {
           if (r < He) S[(1 + r) * CRP + cc] = v;
         });
-        mfma_contract<NT>(opeo, RTo, KSo, S2 + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+        mfma_contract<NT>(opeo, RTo, KSo, S2.row(2 * He), CRP, CT, [&](int r, int cc, double v) {
           if (r < Ho) S[(Fe + 1 + r) * CRP + cc] = v;
         });
       }
@@ -684,14 +708,14 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
             const int i = q >> ets, c0 = q & (ET - 1), c1 = c0 + ET;
 #pragma unroll
             for (int bsel = 0; bsel < 2; ++bsel) {
-              double* B = bsel == 0 ? T : S;
-              const double ar = B[i * CRP + 2 * c0], ai = B[i * CRP + 2 * c0 + 1];
-              const double br = B[i * CRP + 2 * c1], bi = B[i * CRP + 2 * c1 + 1];
+              const LdsBuf B = bsel == 0 ? T : S;
+              const double ar = B.pair(i * CRP + 2 * c0)[0], ai = B.pair(i * CRP + 2 * c0)[1];
+              const double br = B.pair(i * CRP + 2 * c1)[0], bi = B.pair(i * CRP + 2 * c1)[1];
               const double pr = 0.5 * (ar + br), pi = 0.5 * (ai - bi);
-              B[i * CRP + 2 * c0] = pr;
-              B[i * CRP + 2 * c0 + 1] = pi;
-              B[i * CRP + 2 * c1] = pr;
-              B[i * CRP + 2 * c1 + 1] = -pi;
+              B.pair(i * CRP + 2 * c0)[0] = pr;
+              B.pair(i * CRP + 2 * c0)[1] = pi;
+              B.pair(i * CRP + 2 * c1)[0] = pr;
+              B.pair(i * CRP + 2 * c1)[1] = -pi;
             }
           }
           __syncthreads();
@@ -701,12 +725,12 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
           const int kk = q >> cs, c = q & (C - 1);
           if (!col_valid(c)) continue;
           const int re = 1 + kk, ro = Fe + 1 + kk;
-          const double ver = T[re * CRP + 2 * c], vei = T[re * CRP + 2 * c + 1];
-          const double eer = S[re * CRP + 2 * c], eei = S[re * CRP + 2 * c + 1];
+          const double ver = T.pair(re * CRP + 2 * c)[0], vei = T.pair(re * CRP + 2 * c)[1];
+          const double eer = S.pair(re * CRP + 2 * c)[0], eei = S.pair(re * CRP + 2 * c)[1];
           const size_t s1 = st(kk, c);
           if (kk < Ho) {
-            const double vor = T[ro * CRP + 2 * c], voi = T[ro * CRP + 2 * c + 1];
-            const double eor = S[ro * CRP + 2 * c], eoi = S[ro * CRP + 2 * c + 1];
+            const double vor = T.pair(ro * CRP + 2 * c)[0], voi = T.pair(ro * CRP + 2 * c)[1];
+            const double eor = S.pair(ro * CRP + 2 * c)[0], eoi = S.pair(ro * CRP + 2 * c)[1];
             const size_t s2 = st(N - 1 - kk, c);
             const double v1r = ver + vor, v1i = vei + voi, v2r = ver - vor, v2i = vei - voi;
             const double e1r = eer + eor, e1i = eei + eoi, e2r = eer - eor, e2i = eei - eoi;
@@ -716,14 +740,14 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
             a.eta[s2] = e2r; a.eta[s2 + 1] = e2i;
             // halves of the stored (rounded) values, formed exactly as a restart
             // from this state forms them, so that a resumed run is bitwise equal
-            T[re * CRP + 2 * c] = 0.5 * (v1r + v2r);
-            T[re * CRP + 2 * c + 1] = 0.5 * (v1i + v2i);
-            T[ro * CRP + 2 * c] = 0.5 * (v1r - v2r);
-            T[ro * CRP + 2 * c + 1] = 0.5 * (v1i - v2i);
-            S[re * CRP + 2 * c] = 0.5 * (e1r + e2r);
-            S[re * CRP + 2 * c + 1] = 0.5 * (e1i + e2i);
-            S[ro * CRP + 2 * c] = 0.5 * (e1r - e2r);
-            S[ro * CRP + 2 * c + 1] = 0.5 * (e1i - e2i);
+            T.pair(re * CRP + 2 * c)[0] = 0.5 * (v1r + v2r);
+            T.pair(re * CRP + 2 * c)[1] = 0.5 * (v1i + v2i);
+            T.pair(ro * CRP + 2 * c)[0] = 0.5 * (v1r - v2r);
+            T.pair(ro * CRP + 2 * c)[1] = 0.5 * (v1i - v2i);
+            S.pair(re * CRP + 2 * c)[0] = 0.5 * (e1r + e2r);
+            S.pair(re * CRP + 2 * c)[1] = 0.5 * (e1i + e2i);
+            S.pair(ro * CRP + 2 * c)[0] = 0.5 * (e1r - e2r);
+            S.pair(ro * CRP + 2 * c)[1] = 0.5 * (e1i - e2i);
           } else {
             a.v[s1] = ver; a.v[s1 + 1] = vei;
             a.eta[s1] = eer; a.eta[s1 + 1] = eei;
@@ -739,33 +763,33 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         const int re = 1 + kk, ro = Fe + 1 + kk;
         if (kk < Ho) {
           const size_t s2 = st(N - 1 - kk, c);
-          T[re * CRP + 2 * c] = 0.5 * (a.v[s1] + a.v[s2]);
-          T[re * CRP + 2 * c + 1] = 0.5 * (a.v[s1 + 1] + a.v[s2 + 1]);
-          T[ro * CRP + 2 * c] = 0.5 * (a.v[s1] - a.v[s2]);
-          T[ro * CRP + 2 * c + 1] = 0.5 * (a.v[s1 + 1] - a.v[s2 + 1]);
-          S[re * CRP + 2 * c] = 0.5 * (a.eta[s1] + a.eta[s2]);
-          S[re * CRP + 2 * c + 1] = 0.5 * (a.eta[s1 + 1] + a.eta[s2 + 1]);
-          S[ro * CRP + 2 * c] = 0.5 * (a.eta[s1] - a.eta[s2]);
-          S[ro * CRP + 2 * c + 1] = 0.5 * (a.eta[s1 + 1] - a.eta[s2 + 1]);
+          T.pair(re * CRP + 2 * c)[0] = 0.5 * (a.v[s1] + a.v[s2]);
+          T.pair(re * CRP + 2 * c)[1] = 0.5 * (a.v[s1 + 1] + a.v[s2 + 1]);
+          T.pair(ro * CRP + 2 * c)[0] = 0.5 * (a.v[s1] - a.v[s2]);
+          T.pair(ro * CRP + 2 * c)[1] = 0.5 * (a.v[s1 + 1] - a.v[s2 + 1]);
+          S.pair(re * CRP + 2 * c)[0] = 0.5 * (a.eta[s1] + a.eta[s2]);
+          S.pair(re * CRP + 2 * c)[1] = 0.5 * (a.eta[s1 + 1] + a.eta[s2 + 1]);
+          S.pair(ro * CRP + 2 * c)[0] = 0.5 * (a.eta[s1] - a.eta[s2]);
+          S.pair(ro * CRP + 2 * c)[1] = 0.5 * (a.eta[s1 + 1] - a.eta[s2 + 1]);
         } else {
-          T[re * CRP + 2 * c] = a.v[s1];
-          T[re * CRP + 2 * c + 1] = a.v[s1 + 1];
-          S[re * CRP + 2 * c] = a.eta[s1];
-          S[re * CRP + 2 * c + 1] = a.eta[s1 + 1];
+          T.pair(re * CRP + 2 * c)[0] = a.v[s1];
+          T.pair(re * CRP + 2 * c)[1] = a.v[s1 + 1];
+          S.pair(re * CRP + 2 * c)[0] = a.eta[s1];
+          S.pair(re * CRP + 2 * c)[1] = a.eta[s1 + 1];
         }
       }
     }
     __syncthreads();
     // ---- velocity recovery: dv/dy = D1c v (odd <- even, even <- odd) -> S2 FH
     if constexpr (kDer != kDerFP64) {
-      dcontract<kDer, NT>(a, 2, a.D1cT_e, RFo, He, T + CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 2, a.D1cT_e, RFo, He, T.row(1), CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kDer, NT>(a, 3, a.D1cT_o, RFe, Ho, T + size_t(Fe + 1) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 3, a.D1cT_o, RFe, Ho, T.row(Fe + 1), CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) S2[r * CRP + cc] = v;
       });
     } else {
-      const CJob jc[2] = {{a.D1cT_e, RFo, (He + 3) / 4, T + CRP}, {a.D1cT_o, RFe, (Ho + 3) / 4, T + size_t(Fe + 1) * CRP}};
+      const CJob jc[2] = {{a.D1cT_e, RFo, (He + 3) / 4, T.row(1)}, {a.D1cT_o, RFe, (Ho + 3) / 4, T.row(Fe + 1)}};
       mfma_jobs<NT, false>(jc, CRP, CT, [&](int j, int r, int cc, double v) {
         if (j == 0) {
           if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
@@ -787,15 +811,15 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       for (int par = 0; par < 2; ++par) {
         if (par == 1 && !pair) continue;
         const int row = par == 0 ? k : Fe + k;
-        const double dr = S2[row * CRP + 2 * c], di = S2[row * CRP + 2 * c + 1];
-        const double er = S[row * CRP + 2 * c], ei = S[row * CRP + 2 * c + 1];
+        const double dr = S2.pair(row * CRP + 2 * c)[0], di = S2.pair(row * CRP + 2 * c)[1];
+        const double er = S.pair(row * CRP + 2 * c)[0], ei = S.pair(row * CRP + 2 * c)[1];
         // u = (i kx dv - i kz eta) / k^2 ; w = (i kx eta + i kz dv) / k^2
         const double ur = (-kx * di + kz * ei) * ik2, ui = (kx * dr - kz * er) * ik2;
         const double wr = (-kx * ei - kz * di) * ik2, wi = (kx * er + kz * dr) * ik2;
-        S2[row * CRP + 2 * c] = ur;
-        S2[row * CRP + 2 * c + 1] = ui;
-        S[row * CRP + 2 * c] = wr;
-        S[row * CRP + 2 * c + 1] = wi;
+        S2.pair(row * CRP + 2 * c)[0] = ur;
+        S2.pair(row * CRP + 2 * c)[1] = ui;
+        S.pair(row * CRP + 2 * c)[0] = wr;
+        S.pair(row * CRP + 2 * c)[1] = wi;
         uh[par][0] = ur; uh[par][1] = ui;
         wh[par][0] = wr; wh[par][1] = wi;
         dh[par][0] = dr; dh[par][1] = di;
@@ -819,8 +843,8 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     __syncthreads();
     // du/dy = D1 u -> T (FH) and dw/dy = D1 w -> S2 (FH): in one pass when
     // every wave can hold its tiles until u in S2 has been read
-    const CJob jd[4] = {{a.D1T_e, RFo, (Fe + 3) / 4, S2}, {a.D1T_o, RFe, (Fo + 3) / 4, S2 + size_t(Fe) * CRP},
-                        {a.D1T_e, RFo, (Fe + 3) / 4, S}, {a.D1T_o, RFe, (Fo + 3) / 4, S + size_t(Fe) * CRP}};
+    const CJob jd[4] = {{a.D1T_e, RFo, (Fe + 3) / 4, S2.row(0)}, {a.D1T_o, RFe, (Fo + 3) / 4, S2.row(Fe)},
+                        {a.D1T_e, RFo, (Fe + 3) / 4, S.row(0)}, {a.D1T_o, RFe, (Fo + 3) / 4, S.row(Fe)}};
     bool merged = false;
     if constexpr (kDer == kDerFP64) {
       if (mfma_jobs_fit<NT>(jd, CT)) {
@@ -832,17 +856,17 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       }
     }
     if (!merged) {
-      dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, S2, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, S2.row(0), CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) T[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, S2 + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, S2.row(Fe), CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) T[r * CRP + cc] = v;
       });
       __syncthreads();
-      dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, S, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, S.row(0), CRP, CT, [&](int r, int cc, double v) {
         if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
       });
-      dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, S + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+      dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, S.row(Fe), CRP, CT, [&](int r, int cc, double v) {
         if (r < Fe) S2[r * CRP + cc] = v;
       });
     }
@@ -884,19 +908,19 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         const double x1 = a.means[(size_t(comp) * My + k) * E + e];
         const double x2 = a.means[(size_t(comp) * My + j2) * E + e];
         if (k < Fo) {
-          T[k * CRP + 2 * el + comp] = 0.5 * (x1 + x2);
-          T[(Fe + k) * CRP + 2 * el + comp] = 0.5 * (x1 - x2);
+          T.pair(k * CRP + 2 * el)[comp] = 0.5 * (x1 + x2);
+          T.pair((Fe + k) * CRP + 2 * el)[comp] = 0.5 * (x1 - x2);
         } else {
-          T[k * CRP + 2 * el + comp] = x1;
+          T.pair(k * CRP + 2 * el)[comp] = x1;
         }
       }
     }
     __syncthreads();
     // (E_U, E_W) = -D1 (<uv>, <wv>) on interior halves
-    dcontract<kDer, NT>(a, 0, a.D1intT_e, RTo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kDer, NT>(a, 0, a.D1intT_e, RTo, Fe, T.row(0), CRP, CT, [&](int r, int cc, double v) {
       if (r < Ho) S[(2 * He + Ho + r) * CRP + cc] = -v;
     });
-    dcontract<kDer, NT>(a, 1, a.D1intT_o, RTe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    dcontract<kDer, NT>(a, 1, a.D1intT_o, RTe, Fo, T.row(Fe), CRP, CT, [&](int r, int cc, double v) {
       if (r < He) S[(He + r) * CRP + cc] = -v;
     });
     __syncthreads();
@@ -907,7 +931,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       const int kk = even ? hr : hr - He;
       const int rowF = even ? He + kk : 2 * He + Ho + kk;
       const int rowX = even ? kk : 2 * He + kk;
-      double xu = S[rowF * CRP + 2 * el], xw = S[rowF * CRP + 2 * el + 1];
+      double xu = S.pair(rowF * CRP + 2 * el)[0], xw = S.pair(rowF * CRP + 2 * el)[1];
       double* hu = a.hEU + size_t(hr) * E + e;
       double* hw = a.hEW + size_t(hr) * E + e;
       if (s == 0) {
@@ -923,23 +947,23 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
         xu = (*hu + xu) * (1.0 / 6.0);
         xw = (*hw + xw) * (1.0 / 6.0);
       }
-      S[rowF * CRP + 2 * el] = hdt * xu;
-      S[rowF * CRP + 2 * el + 1] = hdt * xw;
+      S.pair(rowF * CRP + 2 * el)[0] = hdt * xu;
+      S.pair(rowF * CRP + 2 * el)[1] = hdt * xw;
       // interior nodes 1 + kk and My - 2 - kk of U0, W0
       const size_t j1 = size_t(1 + kk) * E + e, j2 = size_t(My - 2 - kk) * E + e;
       const bool center = even && kk == Ho;
       const double sg = even ? 1.0 : -1.0;
-      S[rowX * CRP + 2 * el] = center ? a.U[j1] : 0.5 * (a.U[j1] + sg * a.U[j2]);
-      S[rowX * CRP + 2 * el + 1] = center ? a.W[j1] : 0.5 * (a.W[j1] + sg * a.W[j2]);
+      S.pair(rowX * CRP + 2 * el)[0] = center ? a.U[j1] : 0.5 * (a.U[j1] + sg * a.U[j2]);
+      S.pair(rowX * CRP + 2 * el)[1] = center ? a.W[j1] : 0.5 * (a.W[j1] + sg * a.W[j2]);
     }
     __syncthreads();
     // (U_a, W) halves = [A_U | B_U] halves -> T (FH)
     const double* me = a.meanT;
     const double* mo = me + size_t(RTe) * KSe * 64;
-    mfma_contract<NT>(me, RTe, KSe, S, CRP, CT, [&](int r, int cc, double v) {
+    mfma_contract<NT>(me, RTe, KSe, S.row(0), CRP, CT, [&](int r, int cc, double v) {
       if (r < He) T[(1 + r) * CRP + cc] = v;
     });
-    mfma_contract<NT>(mo, RTo, KSo, S + size_t(2 * He) * CRP, CRP, CT, [&](int r, int cc, double v) {
+    mfma_contract<NT>(mo, RTo, KSo, S.row(2 * He), CRP, CT, [&](int r, int cc, double v) {
       if (r < Ho) T[(Fe + 1 + r) * CRP + cc] = v;
     });
     __syncthreads();
@@ -947,13 +971,13 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     for (int q = tid; q < Fe * NM; q += NT) {
       const int k = q >> ets, el = q & (NM - 1);
       if (k == 0) {
-        T[2 * el] = 0.5 * (a.Ubot + a.Utop);
-        T[2 * el + 1] = 0.0;
-        T[Fe * CRP + 2 * el] = 0.5 * (a.Ubot - a.Utop);
-        T[Fe * CRP + 2 * el + 1] = 0.0;
+        T.pair(2 * el)[0] = 0.5 * (a.Ubot + a.Utop);
+        T.pair(2 * el)[1] = 0.0;
+        T.pair(Fe * CRP + 2 * el)[0] = 0.5 * (a.Ubot - a.Utop);
+        T.pair(Fe * CRP + 2 * el)[1] = 0.0;
       } else {
-        T[k * CRP + 2 * el] += a.lift_h[k - 1];
-        if (k - 1 < Ho) T[(Fe + k) * CRP + 2 * el] += a.lift_h[He + k - 1];
+        T.pair(k * CRP + 2 * el)[0] += a.lift_h[k - 1];
+        if (k - 1 < Ho) T.pair((Fe + k) * CRP + 2 * el)[0] += a.lift_h[He + k - 1];
       }
     }
     __syncthreads();
@@ -964,7 +988,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       if (a.poiseuille) {
         double qa = 0.0, wg = 0.0;
         for (int k = 0; k < Fe; ++k) {
-          qa += a.ccw_h[k] * T[k * CRP + 2 * el];
+          qa += a.ccw_h[k] * T.pair(k * CRP + 2 * el)[0];
           if (k >= 1) wg += a.ccw_h[k] * a.green_h[k - 1];
         }
         gam = (a.Qtarget - qa) / wg;
@@ -976,26 +1000,26 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     // gamma response is even (the green function is symmetric)
     for (int q = tid; q < He * NM; q += NT) {
       const int kk = q >> ets, el = q & (NM - 1);
-      T[(1 + kk) * CRP + 2 * el] += gam_s[el] * a.green_h[kk];
+      T.pair((1 + kk) * CRP + 2 * el)[0] += gam_s[el] * a.green_h[kk];
     }
     __syncthreads();
     if (s == 2) {
       for (int q = tid; q < Fe * NM; q += NT) {
         const int k = q >> ets, el = q & (NM - 1), e = m0 + tile * ET + el;
         if (e >= mend) continue;
-        const double ue = T[k * CRP + 2 * el], we = T[k * CRP + 2 * el + 1];
+        const double ue = T.pair(k * CRP + 2 * el)[0], we = T.pair(k * CRP + 2 * el)[1];
         if (k < Fo) {
-          const double uo = T[(Fe + k) * CRP + 2 * el], wo = T[(Fe + k) * CRP + 2 * el + 1];
+          const double uo = T.pair((Fe + k) * CRP + 2 * el)[0], wo = T.pair((Fe + k) * CRP + 2 * el)[1];
           const double u1 = ue + uo, w1 = we + wo, u2 = ue - uo, w2 = we - wo;
           a.U[size_t(k) * E + e] = u1;
           a.W[size_t(k) * E + e] = w1;
           a.U[size_t(My - 1 - k) * E + e] = u2;
           a.W[size_t(My - 1 - k) * E + e] = w2;
           // halves of the stored values, as a restart forms them
-          T[k * CRP + 2 * el] = 0.5 * (u1 + u2);
-          T[k * CRP + 2 * el + 1] = 0.5 * (w1 + w2);
-          T[(Fe + k) * CRP + 2 * el] = 0.5 * (u1 - u2);
-          T[(Fe + k) * CRP + 2 * el + 1] = 0.5 * (w1 - w2);
+          T.pair(k * CRP + 2 * el)[0] = 0.5 * (u1 + u2);
+          T.pair(k * CRP + 2 * el)[1] = 0.5 * (w1 + w2);
+          T.pair((Fe + k) * CRP + 2 * el)[0] = 0.5 * (u1 - u2);
+          T.pair((Fe + k) * CRP + 2 * el)[1] = 0.5 * (w1 - w2);
         } else {
           a.U[size_t(k) * E + e] = ue;
           a.W[size_t(k) * E + e] = we;
@@ -1008,22 +1032,22 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       if (e >= mend) continue;
       const size_t j1 = size_t(k) * E + e, j2 = size_t(My - 1 - k) * E + e;
       if (k < Fo) {
-        T[k * CRP + 2 * el] = 0.5 * (a.U[j1] + a.U[j2]);
-        T[k * CRP + 2 * el + 1] = 0.5 * (a.W[j1] + a.W[j2]);
-        T[(Fe + k) * CRP + 2 * el] = 0.5 * (a.U[j1] - a.U[j2]);
-        T[(Fe + k) * CRP + 2 * el + 1] = 0.5 * (a.W[j1] - a.W[j2]);
+        T.pair(k * CRP + 2 * el)[0] = 0.5 * (a.U[j1] + a.U[j2]);
+        T.pair(k * CRP + 2 * el)[1] = 0.5 * (a.W[j1] + a.W[j2]);
+        T.pair((Fe + k) * CRP + 2 * el)[0] = 0.5 * (a.U[j1] - a.U[j2]);
+        T.pair((Fe + k) * CRP + 2 * el)[1] = 0.5 * (a.W[j1] - a.W[j2]);
       } else {
-        T[k * CRP + 2 * el] = a.U[j1];
-        T[k * CRP + 2 * el + 1] = a.W[j1];
+        T.pair(k * CRP + 2 * el)[0] = a.U[j1];
+        T.pair(k * CRP + 2 * el)[1] = a.W[j1];
       }
     }
   }
   __syncthreads();
   // (0,0) velocity fields: u = U, v = 0, w = W, du/dy = D1 U, dw/dy = D1 W
-  dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, T, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kDer, NT>(a, 4, a.D1T_e, RFo, Fe, T.row(0), CRP, CT, [&](int r, int cc, double v) {
     if (r < Fo) S2[(Fe + r) * CRP + cc] = v;
   });
-  dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, T + size_t(Fe) * CRP, CRP, CT, [&](int r, int cc, double v) {
+  dcontract<kDer, NT>(a, 5, a.D1T_o, RFe, Fo, T.row(Fe), CRP, CT, [&](int r, int cc, double v) {
     if (r < Fe) S2[r * CRP + cc] = v;
   });
   __syncthreads();
@@ -1035,10 +1059,10 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
       const double sg = side == 0 ? 1.0 : -1.0;
       const int j = side == 0 ? k : My - 1 - k;
       const size_t off = 2 * ((size_t(j) * E + e) * K);
-      const double U = T[k * CRP + 2 * el] + (pair ? sg * T[(Fe + k) * CRP + 2 * el] : 0.0);
-      const double W = T[k * CRP + 2 * el + 1] + (pair ? sg * T[(Fe + k) * CRP + 2 * el + 1] : 0.0);
-      const double dU = S2[k * CRP + 2 * el] + (pair ? sg * S2[(Fe + k) * CRP + 2 * el] : 0.0);
-      const double dW = S2[k * CRP + 2 * el + 1] + (pair ? sg * S2[(Fe + k) * CRP + 2 * el + 1] : 0.0);
+      const double U = T.pair(k * CRP + 2 * el)[0] + (pair ? sg * T.pair((Fe + k) * CRP + 2 * el)[0] : 0.0);
+      const double W = T.pair(k * CRP + 2 * el)[1] + (pair ? sg * T.pair((Fe + k) * CRP + 2 * el)[1] : 0.0);
+      const double dU = S2.pair(k * CRP + 2 * el)[0] + (pair ? sg * S2.pair((Fe + k) * CRP + 2 * el)[0] : 0.0);
+      const double dW = S2.pair(k * CRP + 2 * el)[1] + (pair ? sg * S2.pair((Fe + k) * CRP + 2 * el)[1] : 0.0);
       st_c(vel + off, U, 0.0);
       st_c(vel + off + FS, 0.0, 0.0);
       st_c(vel + off + 2 * FS, W, 0.0);
