@@ -1738,7 +1738,9 @@ int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
       for (int e = 0; e < E; ++e)
         for (int j = 0; j < My; ++j)
           for (int m = 0; m < K; ++m) {
-            const size_t d = (((size_t(f) * My + j) * E + e) * K + m) * 2;
+            const int nx = m / h->NZ, iz = m - nx * h->NZ;
+            const int slot = stage_slot(iz < h->P ? iz : iz - h->NZ);
+            const size_t d = (((size_t(f) * My + j) * E + e) * K + size_t(nx) * h->NZ + slot) * 2;
             const size_t o = (((size_t(f) * E + e) * My + j) * K + m) * 2;
             for (int c = 0; c < 2; ++c)
               dst[o + c] = vt == 8 ? reinterpret_cast<const double*>(raw.data())[d + c]

@@ -7,7 +7,8 @@
 //   vel            : complex VT     [5][My][E][K]   u, v, w, du/dy, dw/dy
 //   nl             : complex VT     [3][My][E][K]   advection N_u, N_v, N_w
 // (the two stage buffers are member-outer so that one plane workgroup's
-// spectral input is contiguous; see kernels_plane.hip)
+// spectral input is contiguous; see kernels_plane.hip; within an n_x row their
+// modes are in stage_slot order, below)
 //   means          : double         [2][My][E]      <uv>, <wv>
 //   psum           : double         [NPS][My][E]    plane means for statistics
 //   hist F, G      : complex double [K][N][E]       RK3 forcing history
@@ -23,6 +24,15 @@
 #include <vector>
 
 namespace dns {
+
+// Order of the kz modes within an n_x row of the stage buffers: kz = 0, then
+// +1, -1, +2, -2, ...  A per-mode workgroup owns the pair (+|kz|, -|kz|) of
+// every row, so its loads and stores of the pair fall in one cache line.
+__host__ __device__ constexpr int stage_slot(int nz) { return nz > 0 ? 2 * nz - 1 : -2 * nz; }
+__host__ __device__ constexpr int stage_kz(int slot) { return (slot & 1) ? (slot + 1) >> 1 : -(slot >> 1); }
+static_assert(stage_slot(0) == 0 && stage_slot(1) == 1 && stage_slot(-1) == 2 && stage_slot(-3) == 6 &&
+                  stage_kz(5) == 3 && stage_kz(6) == -3 && stage_kz(0) == 0,
+              "stage slot order");
 
 enum PlaneSum { PS_UU = 0, PS_VV = 1, PS_WW = 2, PS_GRAD = 3, NPS = 4 };
 

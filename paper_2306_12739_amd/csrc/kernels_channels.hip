@@ -49,7 +49,8 @@ __global__ void __launch_bounds__(kCT) spec_to_phys_kernel(const VT* vel, double
   const size_t FS = 2 * size_t(My) * E * K;
   for (int q = threadIdx.x; q < L * NZ; q += kCT) {
     const size_t off = f * FS + 2 * ((size_t(j) * E + e) * K + q);
-    spec[q] = cd{double(vel[off]), double(vel[off + 1])};
+    const int nx = q / NZ, nz = stage_kz(q - nx * NZ);
+    spec[nx * NZ + (nz >= 0 ? nz : nz + NZ)] = cd{double(vel[off]), double(vel[off + 1])};
   }
   __syncthreads();
   for (int q = threadIdx.x; q < L * Mz; q += kCT) {

@@ -226,8 +226,8 @@ __global__ void __launch_bounds__(kWallThreads) wall_sums(const VT* __restrict__
   const VT* row = vel + 2 * ((size_t(j) * E + e) * K);
   double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // uu vv ww grad uv wv
   auto add = [&](int k, const P2 (&g)[5]) {
-    const int nx = k / NZ, iz = k - nx * NZ;
-    const int nz = iz < P ? iz : iz - NZ;
+    const int nx = k / NZ;
+    const int nz = stage_kz(k - nx * NZ);
     const double m = nx == 0 ? 1.0 : 2.0;
     const double kx = kxs * nx, kz = kzs * nz, k2 = kx * kx + kz * kz;
     double f[5][2];

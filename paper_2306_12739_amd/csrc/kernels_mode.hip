@@ -453,10 +453,11 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     const int sl = c >> ets;
     return m0 + tile * ET + (c - sl * ET) < mend && (sl == 0 || az > 0);
   };
-  auto col_mode = [&](int c) { return nx * NZ + (c < ET ? az : NZ - az); };
+  auto col_mode = [&](int c) { return nx * NZ + (c < ET ? az : NZ - az); };  // state arrays
+  auto col_slot = [&](int c) { return nx * NZ + stage_slot(c < ET ? az : -az); };  // stage buffers
   auto col_kz = [&](int c) { return (c < ET ? 1.0 : -1.0) * a.kzs * az; };
   // stage-buffer element (node j, column c) in VT units
-  auto sb = [&](int j, int c) { return 2 * ((size_t(j) * E + col_member(c)) * K + col_mode(c)); };
+  auto sb = [&](int j, int c) { return 2 * ((size_t(j) * E + col_member(c)) * K + col_slot(c)); };
   // state element (interior node i in [0, N), column c)
   auto st = [&](int i, int c) { return 2 * ((size_t(col_mode(c)) * N + i) * E + col_member(c)); };
   const double kx = a.kxs * nx;

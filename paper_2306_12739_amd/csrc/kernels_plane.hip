@@ -162,13 +162,13 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   for (int t = tid; t < PP; t += kNT) rootP[t] = rootZ[t * R];
   __syncthreads();
 
-  // spectral input element (field f, nx, iz) of this (j, e), as complex T
+  // spectral input element (field f, nx, stage slot iz) of this (j, e), as complex T
   auto vel_at = [&](int f, int nx, int iz) -> C {
     const size_t off = ((size_t(f) * My + j) * E + e) * K + size_t(nx) * NZ + iz;
     return ldc<T>(vel + 2 * off);
   };
 
-  // register accumulators of the forward transform: flat (f, nx, iz)
+  // register accumulators of the forward transform: flat (f, stage-buffer position)
   C acc[Cfg::NACC];
 #pragma unroll
   for (int k = 0; k < Cfg::NACC; ++k) acc[k] = C{T(0), T(0)};
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
           if (n < P) nz = n;
           else if (n > MZ - P) nz = n - MZ;
           else continue;
-          const int izs = nz >= 0 ? nz : nz + NZ;
+          const int izs = stage_slot(nz);
           C x;
           if constexpr (kind == 2) {
             const T kz = kzs * T(nz), kx = kxs * T(nx);
@@ -443,8 +443,8 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
       if (idx < 3 * L * NZ) {
         const int f = idx / (L * NZ);
         const int rem = idx - f * L * NZ;
-        const int nx = rem / NZ, iz = rem - nx * NZ;
-        const int nz = iz < P ? iz : iz - NZ;
+        const int nx = rem / NZ;
+        const int nz = stage_kz(rem - nx * NZ);  // rem: the mode's stage-buffer position
         const int kk = ((nz % PP) + PP) % PP;
         const int t = (((r * nz) % MZ) + MZ) % MZ;
         acc[k] = cadd(acc[k], cmul(zb[(f * L + nx) * Cfg::PPP + kk], rootZ[t]));

@@ -247,7 +247,7 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
         if (n < P) nz = n;
         else if (n > MZ - P) nz = n - MZ;
         else continue;
-        const C x = ld2<T>(col + 2 * (nz >= 0 ? nz : nz + NZ));
+        const C x = ld2<T>(col + 2 * stage_slot(nz));
         const C xt = cmul(x, cconj(rootZ[(n * r) % MZ]));
         y0 = cadd(y0, xt);
         if (src < 3) y1 = cadd(y1, cmuli<1>(cscale(xt, kzs * T(nz))));
@@ -448,8 +448,8 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
     for (int km = 0; km < Cfg::NM; ++km) {
       const int m = tbase + km * NT;
       if (m < K) {
-        const int nx = m / NZ, iz = m - nx * NZ;
-        const int nz = iz < P ? iz : iz - NZ;
+        const int nx = m / NZ;
+        const int nz = stage_kz(m - nx * NZ);  // m: the mode's stage-buffer position
         const int kk = ((nz % PP) + PP) % PP;
         const int tt = (((r * nz) % MZ) + MZ) % MZ;
         const C w = rootZ[tt];
