@@ -366,7 +366,8 @@ const char* dns_last_error(const dns_handle* h);
  * kernel and every admissible member tile of the per-mode kernel on the current
  * state (HIP events on the handle's stream, 5 launches each, the per-mode
  * kernel at its second sub-step; the state does not advance) and keeps the
- * fastest of each for the current precision.  Tile shapes change the order of
+ * fastest of each for the current precision; the current member tile stays
+ * unless another is more than 2 % faster.  Tile shapes change the order of
  * floating-point operations in the FFTs, never the method.
  *   cache_path : optional text file (NULL: none).  A line "<precision> <Nx>
  *                <Ny> <Nz> <members> <plane_rows> <mode_members> <plane_ms>

@@ -1845,15 +1845,21 @@ int tune_one(dns_handle* h, const char* cache, dns_tuning* out) {
   plane_var(h) = best_v;
   // the mode kernel's second sub-step on the current stage buffers (the next
   // step rewrites its history first)
-  int best_et = h->ET;
+  // the current tile is timed first and another replaces it only when faster
+  // by more than kTileMargin: member tiles often tie within timing noise, and
+  // a choice that flips between runs would change what a run measures
+  constexpr double kTileMargin = 0.02;
+  const int et0 = h->ET;
+  int best_et = et0;
   double best_m = 1e30;
-  for (int et = 1; et <= 8; et *= 2) {
-    if (!mode_tile_ok(h, et)) continue;
+  for (int i = 0; i <= 4; ++i) {
+    const int et = i == 0 ? et0 : 1 << (i - 1);
+    if ((i > 0 && et == et0) || !mode_tile_ok(h, et)) continue;
     set_mode_tile(h, et);
     double ms;
     const int rc = time_launches(h, kReps, [&] { return launch_mode(h->precision, mode_args(h, 1), h->stream); }, &ms);
     if (rc) return rc;
-    if (ms < best_m) best_m = ms, best_et = et;
+    if (i == 0 || ms < (1.0 - kTileMargin) * best_m) best_m = ms, best_et = et;
   }
   set_mode_tile(h, best_et);
   h->vel_fresh = false;
