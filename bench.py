@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tile shapes instead of running the tuner first")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuner cache file: a tiling found there is applied without timing and new "
+                         "results are appended, so that several runs (profiler passes) use one choice")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--advection", choices=["advective", "rotational"], default="advective",
                     help="form of the nonlinear term for the headline run; the other form is "
@@ -262,7 +265,7 @@ def main():
     forms = {"advective": dns.ADV_ADVECTIVE, "rotational": dns.ADV_ROTATIONAL}
     ens.set_advection(forms[args.advection])
     ens.set_state(*inputs.workload_state(name, ensemble=E))
-    tuning = None if args.no_tune else ens.tune()
+    tuning = None if args.no_tune else ens.tune(args.tune_cache)
 
     ens.step(args.warmup)
     torch.cuda.synchronize()
@@ -294,7 +297,7 @@ def main():
     ens.set_advection(forms[other])
     ens.set_state(*inputs.workload_state(name, ensemble=E))
     if not args.no_tune:
-        ens.tune()
+        ens.tune(args.tune_cache)
     o_steps = max(20, args.steps // 4)
     o_ms = time_steps(ens, stream, 10, o_steps)
     o_plane_ms, _ = ens.kernel_times(args.kernel_reps)
@@ -309,7 +312,7 @@ def main():
         ens.set_precision(dns.PREC_FP64)
         ens.set_state(*inputs.workload_state(name, ensemble=E))
         if not args.no_tune:
-            ens.tune()
+            ens.tune(args.tune_cache)
         f_steps = max(20, args.steps // 2)
         f_ms = time_steps(ens, stream, 5, f_steps)
         fp64 = {"steps": f_steps, "ms_per_step": f_ms / f_steps, "value": E * f_steps / (f_ms / 1e3)}
