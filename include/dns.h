@@ -127,7 +127,8 @@ int dns_group_handle(dns_handle* h, int group, dns_handle** out);
                                  1, 2, 4 or 8, fitting 160 KB of LDS; the tile
                                  runs in workgroups of 512 threads when two fit
                                  a CU, else of 1024 when one does.  Default: the
-                                 largest tile giving sixteen waves per CU      */
+                                 largest tile of which two 512-thread workgroups
+                                 fit a CU, else the largest in one of 1024     */
 #define DNS_OPT_CHAINS 7      /* value: 1..DNS_MAX_CHAINS (<= ensemble): the members
                                  are advanced in this many contiguous chains, each
                                  on a stream of its own forked from and joined

@@ -1123,20 +1123,22 @@ int mode_tile_threads(int My, int ET) {
   return kModeThreadsNarrow;
 }
 
-// Largest ET in {1, 2, 4, 8} (<= E) whose workgroups give sixteen waves per CU
-// (two of 512 threads, or one of 1024); with narrow_only, whose LDS allows two
-// 512-thread workgroups per CU.
+// Default member tile: the largest ET in {1, 2, 4, 8} (<= E) of which two
+// 512-thread workgroups fit a CU's LDS (sixteen waves per CU; measured faster
+// than one 1024-thread workgroup of twice the tile, or level with it); when
+// no tile allows two, the largest that fits one 1024-thread workgroup (with
+// narrow_only: ET = 1).
 int mode_member_tile(int My, int E, bool narrow_only) {
-  int best = 1;
+  int two_best = 0, wide_best = 1;
   for (int et = 1; et <= 8 && et <= E; et *= 2) {
     int crp, sr, tr;
     mode_lds_geometry(My, et, &crp, &sr, &tr);
     const size_t dyn = size_t(2 * sr + tr) * crp * sizeof(double);
-    const bool two = 2 * (dyn + mode_static_lds(kModeThreadsNarrow)) <= kLdsPerCU;
-    const bool wide = dyn + mode_static_lds(kModeThreadsWide) <= kLdsPerCU;
-    if (two || (wide && !narrow_only)) best = et;
+    if (2 * (dyn + mode_static_lds(kModeThreadsNarrow)) <= kLdsPerCU) two_best = et;
+    if (dyn + mode_static_lds(kModeThreadsWide) <= kLdsPerCU) wide_best = et;
   }
-  return best;
+  if (two_best > 0) return two_best;
+  return narrow_only ? 1 : wide_best;
 }
 
 namespace {
