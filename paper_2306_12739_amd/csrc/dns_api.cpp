@@ -1720,6 +1720,22 @@ const char* dns_last_error(const dns_handle* h) {
   return h ? h->err.c_str() : g_thread_err.c_str();
 }
 
+// For every row length NZ = 2P - 1 the library builds: the kz in (-P, P) fill
+// the stage slots [0, NZ) once each, stage_kz inverts stage_slot, and +kz and
+// -kz sit in neighbouring slots (the per-mode kernel's paired accesses).
+constexpr bool stage_order_ok() {
+  for (int P = 1; P <= 256; ++P) {
+    const int NZ = 2 * P - 1;
+    for (int nz = 1 - P; nz < P; ++nz) {
+      const int s = stage_slot(nz);
+      if (s < 0 || s >= NZ || stage_kz(s) != nz) return false;
+      if (nz > 0 && stage_slot(-nz) != s + 1) return false;
+    }
+  }
+  return true;
+}
+static_assert(stage_order_ok(), "stage slot order");
+
 int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
   ORDER_AFTER_PARENT(h);
