@@ -1735,6 +1735,25 @@ constexpr bool stage_order_ok() {
   return true;
 }
 static_assert(stage_order_ok(), "stage slot order");
+// stage_off maps (row, member, mode) of small buffers onto [0, rows E K) once
+// each, and a member's modes lie 1 << stage_block_log2(E) elements apart.
+constexpr bool stage_off_ok() {
+  for (int E = 1; E <= 9; ++E)
+    for (int K = 1; K <= 7; ++K) {
+      bool seen[2 * 9 * 7] = {};
+      const int lb = stage_block_log2(E);
+      for (int r = 0; r < 2; ++r)
+        for (int e = 0; e < E; ++e)
+          for (int k = 0; k < K; ++k) {
+            const size_t o = stage_off(r, e, k, E, K, lb);
+            if (o >= size_t(2 * E * K) || seen[o]) return false;
+            seen[o] = true;
+            if (k + 1 < K && stage_off(r, e, k + 1, E, K, lb) != o + (size_t(1) << lb)) return false;
+          }
+    }
+  return true;
+}
+static_assert(stage_off_ok(), "stage member blocks");
 
 int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
   if (!h) return fail(nullptr, DNS_E_STATE, "handle is NULL");
@@ -1756,7 +1775,7 @@ int dns_debug_stage0(dns_handle* h, double* vel, double* nl, double* means) {
           for (int m = 0; m < K; ++m) {
             const int nx = m / h->NZ, iz = m - nx * h->NZ;
             const int slot = stage_slot(iz < h->P ? iz : iz - h->NZ);
-            const size_t d = (((size_t(f) * My + j) * E + e) * K + size_t(nx) * h->NZ + slot) * 2;
+            const size_t d = stage_off(size_t(f) * My + j, e, nx * h->NZ + slot, E, K, stage_block_log2(E)) * 2;
             const size_t o = (((size_t(f) * E + e) * My + j) * K + m) * 2;
             for (int c = 0; c < 2; ++c)
               dst[o + c] = vt == 8 ? reinterpret_cast<const double*>(raw.data())[d + c]

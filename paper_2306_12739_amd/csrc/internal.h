@@ -6,9 +6,9 @@
 //   state U, W     : double         [My][E]         walls included
 //   vel            : complex VT     [5][My][E][K]   u, v, w, du/dy, dw/dy
 //   nl             : complex VT     [3][My][E][K]   advection N_u, N_v, N_w
-// (the two stage buffers are member-outer so that one plane workgroup's
-// spectral input is contiguous; see kernels_plane.hip; within an n_x row their
-// modes are in stage_slot order, below)
+// (the two stage buffers are member-outer in blocks of B = 2 members when E is
+// even, below: [f][My][E/B][K][B], so that one plane workgroup's spectral input
+// is a stride-B run; within an n_x row their modes are in stage_slot order)
 //   means          : double         [2][My][E]      <uv>, <wv>
 //   psum           : double         [NPS][My][E]    plane means for statistics
 //   hist F, G      : complex double [K][N][E]       RK3 forcing history
@@ -33,6 +33,19 @@ __host__ __device__ constexpr int stage_kz(int slot) { return (slot & 1) ? (slot
 static_assert(stage_slot(0) == 0 && stage_slot(1) == 1 && stage_slot(-1) == 2 && stage_slot(-3) == 6 &&
                   stage_kz(5) == 3 && stage_kz(6) == -3 && stage_kz(0) == 0,
               "stage slot order");
+
+// Members of the stage buffers come in pairs when E is even (log2 of the block
+// returned), innermost: a per-mode workgroup's values of one mode, node and
+// field for two members then share a cache line, while an advection workgroup's
+// row of modes (one member) keeps a stride of two elements.  Blocks of four
+// made the advection kernel's strided rows cost more than the per-mode kernel
+// saved.
+__host__ __device__ constexpr int stage_block_log2(int E) { return E % 2 == 0 ? 1 : 0; }
+// Complex-element offset of (row r = field * My + node, member e, stage
+// position k) in a stage buffer of E members and K modes, blocks of 1 << lb.
+__host__ __device__ constexpr size_t stage_off(size_t r, int e, int k, int E, int K, int lb) {
+  return (((r * size_t(E >> lb) + size_t(e >> lb)) * size_t(K) + size_t(k)) << lb) + size_t(e & ((1 << lb) - 1));
+}
 
 enum PlaneSum { PS_UU = 0, PS_VV = 1, PS_WW = 2, PS_GRAD = 3, NPS = 4 };
 

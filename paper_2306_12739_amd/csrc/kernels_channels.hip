@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kCT) spec_to_phys_kernel(const VT* vel, double
   const int P = (NZ + 1) / 2;
   const size_t FS = 2 * size_t(My) * E * K;
   for (int q = threadIdx.x; q < L * NZ; q += kCT) {
-    const size_t off = f * FS + 2 * ((size_t(j) * E + e) * K + q);
+    const size_t off = f * FS + 2 * stage_off(j, e, q, E, K, stage_block_log2(E));
     const int nx = q / NZ, nz = stage_kz(q - nx * NZ);
     spec[nx * NZ + (nz >= 0 ? nz : nz + NZ)] = cd{double(vel[off]), double(vel[off + 1])};
   }

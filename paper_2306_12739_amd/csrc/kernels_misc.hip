@@ -157,16 +157,18 @@ __global__ void member_mean(VT* __restrict__ nl, double* __restrict__ means, int
     if (idx < ncol) {
       const int k = int(idx % NZ);
       const size_t fj = idx / NZ;  // f * My + j
-      VT* base = nl + 2 * (fj * E * K + k);
+      const int lb = stage_block_log2(E);
       double re = 0.0, im = 0.0;
       for (int e = 0; e < E; ++e) {
-        re += double(base[2 * size_t(e) * K]);
-        im += double(base[2 * size_t(e) * K + 1]);
+        const VT* p = nl + 2 * stage_off(fj, e, k, E, K, lb);
+        re += double(p[0]);
+        im += double(p[1]);
       }
       const VT r = VT(re * inv), i = VT(im * inv);
       for (int e = 0; e < E; ++e) {
-        base[2 * size_t(e) * K] = r;
-        base[2 * size_t(e) * K + 1] = i;
+        VT* p = nl + 2 * stage_off(fj, e, k, E, K, lb);
+        p[0] = r;
+        p[1] = i;
       }
     } else {
       double* row = means + (idx - ncol) * E;  // [2][My] rows of E members
@@ -223,7 +225,8 @@ __global__ void __launch_bounds__(kWallThreads) wall_sums(const VT* __restrict__
   const int e = e0 + int(blockIdx.x >> 1);
   const int j = (blockIdx.x & 1) ? My - 1 : 0;
   const size_t FS = 2 * size_t(My) * E * K;  // field stride (VT units)
-  const VT* row = vel + 2 * ((size_t(j) * E + e) * K);
+  const int lb = stage_block_log2(E);
+  const VT* row = vel + 2 * stage_off(j, e, 0, E, K, lb);  // mode k at row + (2 k << lb)
   double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // uu vv ww grad uv wv
   auto add = [&](int k, const P2 (&g)[5]) {
     const int nx = k / NZ;
@@ -256,8 +259,8 @@ __global__ void __launch_bounds__(kWallThreads) wall_sums(const VT* __restrict__
     P2 ga[5], gb[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      ga[c] = *reinterpret_cast<const P2*>(row + c * FS + 2 * k);
-      gb[c] = *reinterpret_cast<const P2*>(row + c * FS + 2 * k2);
+      ga[c] = *reinterpret_cast<const P2*>(row + c * FS + (2 * size_t(k) << lb));
+      gb[c] = *reinterpret_cast<const P2*>(row + c * FS + (2 * size_t(k2) << lb));
     }
     add(k, ga);
     if (k + kWallThreads < K) add(k2, gb);

@@ -457,7 +457,8 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
   auto col_slot = [&](int c) { return nx * NZ + stage_slot(c < ET ? az : -az); };  // stage buffers
   auto col_kz = [&](int c) { return (c < ET ? 1.0 : -1.0) * a.kzs * az; };
   // stage-buffer element (node j, column c) in VT units
-  auto sb = [&](int j, int c) { return 2 * ((size_t(j) * E + col_member(c)) * K + col_slot(c)); };
+  const int slb = stage_block_log2(E);
+  auto sb = [&](int j, int c) { return 2 * stage_off(j, col_member(c), col_slot(c), E, K, slb); };
   // state element (interior node i in [0, N), column c)
   auto st = [&](int i, int c) { return 2 * ((size_t(col_mode(c)) * N + i) * E + col_member(c)); };
   const double kx = a.kxs * nx;
@@ -1059,7 +1060,7 @@ __device__ __forceinline__ void mode_body(const ModeArgs& a, int flat) {
     for (int side = 0; side < (pair ? 2 : 1); ++side) {
       const double sg = side == 0 ? 1.0 : -1.0;
       const int j = side == 0 ? k : My - 1 - k;
-      const size_t off = 2 * ((size_t(j) * E + e) * K);
+      const size_t off = 2 * stage_off(j, e, 0, E, K, stage_block_log2(E));
       const double U = T.pair(k * CRP + 2 * el)[0] + (pair ? sg * T.pair((Fe + k) * CRP + 2 * el)[0] : 0.0);
       const double W = T.pair(k * CRP + 2 * el)[1] + (pair ? sg * T.pair((Fe + k) * CRP + 2 * el)[1] : 0.0);
       const double dU = S2.pair(k * CRP + 2 * el)[0] + (pair ? sg * S2.pair((Fe + k) * CRP + 2 * el)[0] : 0.0);

@@ -142,6 +142,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
   const int tid = threadIdx.x;
   const int flat = xcd_logical(blockIdx.x, gridDim.x);
   const int E = a.E, K = a.K, My = a.My;
+  const int slb = stage_block_log2(E);  // stage-buffer member blocks
   const int jl = flat / a.ec;
   const int j = a.j0 + jl, e = a.e0 + (flat - jl * a.ec);
   const VT* vel = static_cast<const VT*>(a.vel);
@@ -164,7 +165,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
 
   // spectral input element (field f, nx, stage slot iz) of this (j, e), as complex T
   auto vel_at = [&](int f, int nx, int iz) -> C {
-    const size_t off = ((size_t(f) * My + j) * E + e) * K + size_t(nx) * NZ + iz;
+    const size_t off = stage_off(size_t(f) * My + j, e, nx * NZ + iz, E, K, slb);
     return ldc<T>(vel + 2 * off);
   };
 
@@ -462,7 +463,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     if (idx < 3 * L * NZ) {
       const int f = idx / (L * NZ);
       const int m = idx - f * L * NZ;
-      const size_t off = ((size_t(f) * My + j) * E + e) * K + m;
+      const size_t off = stage_off(size_t(f) * My + j, e, m, E, K, slb);
       stc<T>(nl + 2 * off, cscale(acc[k], inv));
     }
   }

@@ -195,6 +195,7 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
   const int tid = threadIdx.x;
   const int flat = xcd_remap(blockIdx.x, gridDim.x);
   const int E = a.E, My = a.My;
+  const int slb = stage_block_log2(E);  // stage-buffer member blocks
   const int jl = flat / a.ec;
   const int j = a.j0 + jl, e = a.e0 + (flat - jl * a.ec);
   const VT* vel = static_cast<const VT*>(a.vel);
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
       const int rest = it / PP;
       const int nx = rest % L, src = rest / L;
       C y0{T(0), T(0)}, y1{T(0), T(0)};
-      const VT* col = vel + 2 * (((size_t(src) * My + j) * E + e) * K + size_t(nx) * NZ);
+      const VT* col = vel + 2 * stage_off(size_t(src) * My + j, e, nx * NZ, E, K, slb);
 #pragma unroll
       for (int fa = 0; fa < R; ++fa) {
         const int n = np + PP * fa;
@@ -247,7 +248,7 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
         if (n < P) nz = n;
         else if (n > MZ - P) nz = n - MZ;
         else continue;
-        const C x = ld2<T>(col + 2 * stage_slot(nz));
+        const C x = ld2<T>(col + (2 * stage_slot(nz) << slb));
         const C xt = cmul(x, cconj(rootZ[(n * r) % MZ]));
         y0 = cadd(y0, xt);
         if (src < 3) y1 = cadd(y1, cmuli<1>(cscale(xt, kzs * T(nz))));
@@ -457,7 +458,7 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
         for (int f = 0; f < 3; ++f) {
           const C term = cmul(Yb[(f * L + nx) * Cfg::YP + kk], w);
           if constexpr (kGAcc) {
-            VT* pn = nl + 2 * (((size_t(f) * My + j) * E + e) * K + m);
+            VT* pn = nl + 2 * stage_off(size_t(f) * My + j, e, m, E, K, slb);
             C v = r > 0 ? cadd(ld2<T>(pn), term) : term;
             if (r == R - 1) v = cscale(v, inv);
             st2<T>(pn, v);
@@ -478,7 +479,7 @@ __global__ void __launch_bounds__((PP / 2) * L) plane_wave_kernel(PlaneArgs a) {
       if (m < K) {
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
-          const size_t off = ((size_t(f) * My + j) * E + e) * K + m;
+          const size_t off = stage_off(size_t(f) * My + j, e, m, E, K, slb);
           st2<T>(nl + 2 * off, cscale(acc[f * Cfg::NM + km], inv));
         }
       }
