@@ -4,8 +4,8 @@
 // Device layouts (members innermost, "E" = ensemble size):
 //   state v, eta   : complex double [K][N][E]       K = Nx/2 * (Nz-1) modes
 //   state U, W     : double         [My][E]         walls included
-//   vel            : complex VT     [5][My][E][K]   u, v, w, du/dy, dw/dy
-//   nl             : complex VT     [3][My][E][K]   advection N_u, N_v, N_w
+//   vel            : complex VT     [5][My][E/B][K][B]  u, v, w, du/dy, dw/dy
+//   nl             : complex VT     [3][My][E/B][K][B]  advection N_u, N_v, N_w
 // (the two stage buffers are member-outer in blocks of B = 2 members when E is
 // even, below: [f][My][E/B][K][B], so that one plane workgroup's spectral input
 // is a stride-B run; within an n_x row their modes are in stage_slot order)
@@ -72,8 +72,8 @@ struct ModeArgs {
   double* hEU;   // [N][E]
   double* hEW;
   // pseudo-spectral stage buffers
-  void* vel;          // complex VT [5][My][E][K] (written)
-  const void* nl;     // complex VT [3][My][E][K] (read)
+  void* vel;          // complex VT [5][My][E/B][K][B] (written; B = stage member block)
+  const void* nl;     // complex VT [3][My][E/B][K][B] (read)
   const double* means;  // [2][My][E]
   // operators, split by y parity and pre-tiled for v_mfma_f64_16x16x4f64 (see
   // tile_for_mfma): He = ceil(N/2), Ho = floor(N/2), Fe = He + 1, Fo = Ho + 1

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(kNT) plane_kernel(PlaneArgs a) {
     // ---- z inverse of NF spectral fields into zb[fi][q][nx] ----------------
     // The fold y[n'] = sum_a x[n' + PP a] e^{2 pi i (n' + PP a) r / Mz} is done
     // first, by the whole workgroup with consecutive threads on consecutive kz
-    // (contiguous in the member-outer stage buffer), into zb[fi][n'][nx]; the
+    // (a short-stride run of the member-outer stage buffer), into zb[fi][n'][nx]; the
     // transform then reads LDS only and writes its output back to zb.
     // kind 0: fields fbase.. as stored; 1: times i kz; 2: the vorticity
     auto zinv = [&](auto nf_tag, int fbase, auto kind_tag) {
